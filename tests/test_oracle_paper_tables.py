@@ -1,0 +1,114 @@
+"""Reproduction of the paper's printed numbers (Section 4, Tables 1 and 2).
+
+Readings (recorded in the design notes):
+  * the tables' h is the spacing of the zoomed grid; the input spacing is 2h,
+    nodes -1 + 2hk, n = 1/h + 1 per side, output (2n-1)^2 points on [-1,1]^2;
+  * samples outside [-1,1]^2 are f itself (ghost samples): row 1 of Table 1,
+    12/19, comes out only then (clamping gives 2/3);
+  * the neighbour weight that reproduces row 2 of Table 1 is h^2/8 (the value
+    written in the proof of Theorem 1); the definitions print h^2/4, which
+    gives 1.10E-01 instead of 1.33E-01 for row 2;
+  * the indicator scale is the integration-interval length (the literal
+    sqrt(2)h scale moves rows 7-10 by 2-4 %, beyond the printed digits);
+  * L2 values differ from ours by a constant factor (norm normalisation not
+    stated), so only the L2 orders are compared.
+"""
+import os
+
+import numpy as np
+import pytest
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+M = 6
+
+
+def _load(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(t) for t in line.split()])
+    return np.array(rows)
+
+
+def f1(x, y):
+    return 1.0 / (x * x + y * y + 1.0)
+
+
+def f2(x, y):
+    return f1(x, y) + (x < 0)
+
+
+def errors(oracle_mod, fn, i, beta, nbw_factor=0.125, si_mode=0):
+    ht = 2.0 ** (-i)
+    hin = 2 * ht
+    n = int(round(2 / hin)) + 1
+    x = -1 + np.arange(-M, n + M) * hin
+    V = fn(x[:, None], x[None, :])
+    U = oracle_mod.zoom2x(V, beta=beta, keps=1e-8, h=hin, si_mode=si_mode, nbw=nbw_factor * hin * hin)
+    U = U[2 * M: 2 * M + 2 * n - 1, 2 * M: 2 * M + 2 * n - 1]
+    xo = -1 + np.arange(2 * n - 1) * ht
+    E = np.abs(U - fn(xo[:, None], xo[None, :]))
+    right = np.broadcast_to(xo[:, None] >= 0, E.shape)
+    rms = lambda e: np.sqrt(np.mean(e ** 2))
+    return E.max(), rms(E), E[right].max(), rms(E[right])
+
+
+def test_table1_row1_is_12_over_19(oracle_mod):
+    linf = errors(oracle_mod, f1, 0, beta=1.0)[0]
+    assert abs(linf - 12.0 / 19.0) <= 1e-12
+
+
+def test_table1_row1_rejects_clamped_boundary(oracle_mod):
+    # without ghost samples the centre point is 1/3 and the error 2/3
+    V = f1(np.array([-1.0, 1.0])[:, None], np.array([-1.0, 1.0])[None, :])
+    U = oracle_mod.zoom2x(V, beta=1.0, h=2.0)
+    assert abs(abs(U[1, 1] - 1.0) - 2.0 / 3.0) <= 1e-12
+
+
+@pytest.mark.parametrize("i", range(11))
+def test_table1_linf(oracle_mod, i):
+    tab = _load("table1_convergence.txt")
+    linf = errors(oracle_mod, f1, i, beta=1.0)[0]
+    rel = abs(linf / tab[i, 1] - 1)
+    # rows 1, 2 and 9-11 agree to the printed three digits; rows 3-8 within 6 %
+    tol = 0.006 if i in (0, 1, 8, 9, 10) else 0.06
+    assert rel <= tol, (i, linf, tab[i, 1])
+
+
+def test_table1_neighbour_weight_quarter_misses_row2(oracle_mod):
+    tab = _load("table1_convergence.txt")
+    linf = errors(oracle_mod, f1, 1, beta=1.0, nbw_factor=0.25)[0]
+    assert abs(linf / tab[1, 1] - 1) > 0.1
+
+
+def test_table1_orders(oracle_mod):
+    tab = _load("table1_convergence.txt")
+    e = [errors(oracle_mod, f1, i, beta=1.0) for i in range(6, 11)]
+    for k in range(1, 5):
+        o_inf = np.log2(e[k - 1][0] / e[k][0])
+        o_l2 = np.log2(e[k - 1][1] / e[k][1])
+        assert abs(o_inf - tab[6 + k, 2]) <= 0.05
+        assert abs(o_l2 - tab[6 + k, 4]) <= 0.05
+
+
+def test_table1_literal_indicator_scale_misses_fine_rows(oracle_mod):
+    tab = _load("table1_convergence.txt")
+    linf = errors(oracle_mod, f1, 6, beta=1.0, si_mode=1)[0]
+    assert abs(linf / tab[6, 1] - 1) > 0.02
+
+
+@pytest.mark.parametrize("group,beta,region", [(0, 2.0, "all"), (1, 0.0, "right"), (2, 1.0, "right"), (3, 2.0, "right")])
+def test_table2_orders(oracle_mod, group, beta, region):
+    tab = _load("table2_discontinuity.txt")
+    e = [errors(oracle_mod, f2, i, beta=beta) for i in (6, 7, 8)]
+    sel = (0, 1) if region == "all" else (2, 3)
+    for k, row in ((1, 6), (2, 7)):
+        o_inf = np.log2(e[k - 1][sel[0]] / e[k][sel[0]])
+        o_l2 = np.log2(e[k - 1][sel[1]] / e[k][sel[1]])
+        t_inf, t_l2 = tab[row, 1 + 2 * group], tab[row, 2 + 2 * group]
+        # the L_inf order of the one-sided beta = 2 column oscillates between
+        # 3.5 and 3.9 in the table and here; the others settle to 0, 2 or 0.5
+        tol_inf = 0.35 if (group == 3) else 0.1
+        assert abs(o_inf - t_inf) <= tol_inf, (row, o_inf, t_inf)
+        assert abs(o_l2 - t_l2) <= 0.1, (row, o_l2, t_l2)
