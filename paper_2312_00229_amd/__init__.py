@@ -1,0 +1,207 @@
+"""WD-WENO 2x image zooming on MI355X (gfx950).
+
+Python binding of the HIP library (include/weno_zoom.h).  Every step of the
+method runs in the library's kernels; this module only builds tensor
+descriptors, allocates outputs with torch and passes torch's current HIP
+stream.  Method: Crnkovic, Skific, Bosner, "WENO based adaptive image zooming
+algorithm", arXiv 2312.00229, Section 3.
+
+Tensor layouts: a tensor of 2 (H, W), 3 (C, H, W) or 4 (N, C, H, W) dims, of
+dtype uint8 or float32, with any strides -- an HWC image is passed as
+`img.permute(2, 0, 1)` and gets an HWC-strided result back.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import WenoBatchPlan, WenoError, WenoParams, WenoTensor
+
+__all__ = [
+    "Params",
+    "zoom2x",
+    "zoom2x_",
+    "zoom2x_batched",
+    "BatchedZoom",
+    "zoom2x_cascade",
+    "zoom2x_backward",
+    "WenoZoom2x",
+    "set_launch_config",
+    "get_launch_config",
+    "WenoError",
+]
+
+
+@dataclass(frozen=True)
+class Params:
+    beta: float = 2.0
+    k_eps: float = 1e-8
+    h: float = 1.0
+    nbw: float = -1.0  # < 0: h^2 / 4
+
+    def c(self) -> WenoParams:
+        return WenoParams(float(self.beta), float(self.k_eps), float(self.h), float(self.nbw))
+
+
+_DT = {torch.uint8: _lib.WENO_U8, torch.float32: _lib.WENO_F32}
+
+
+def _as4d(t: torch.Tensor) -> torch.Tensor:
+    if t.dim() == 2:
+        return t.unsqueeze(0).unsqueeze(0)
+    if t.dim() == 3:
+        return t.unsqueeze(0)
+    if t.dim() == 4:
+        return t
+    raise ValueError("expected a tensor of 2, 3 or 4 dims (.., H, W), got %d" % t.dim())
+
+
+def _desc(t: torch.Tensor) -> WenoTensor:
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU (got %s)" % t.device)
+    if t.dtype not in _DT:
+        raise ValueError("dtype must be uint8 or float32 (got %s)" % t.dtype)
+    t4 = _as4d(t)
+    n, c, h, w = t4.shape
+    sn, sc, sh, sw = t4.stride()
+    return WenoTensor(t4.data_ptr(), _DT[t.dtype], n, c, h, w, sn, sc, sh, sw)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _params(params, beta, k_eps, h, nbw) -> WenoParams:
+    if params is None:
+        params = Params(beta=beta, k_eps=k_eps, h=h, nbw=nbw)
+    return params.c()
+
+
+def _empty_like_layout(x: torch.Tensor, scale: int, dtype) -> torch.Tensor:
+    """Output of shape (..., scale H, scale W) in x's memory layout (planar or
+    channels-interleaved)."""
+    shape = list(x.shape)
+    shape[-2] *= scale
+    shape[-1] *= scale
+    if x.dim() >= 3 and x.stride(-3) == 1 and x.shape[-3] > 1:
+        # channels interleaved (HWC / NHWC) viewed as (.., C, H, W)
+        perm_shape = shape[:-3] + [shape[-2], shape[-1], shape[-3]]
+        out = torch.empty(perm_shape, dtype=dtype, device=x.device)
+        nd = out.dim()
+        return out.permute(*range(nd - 3), nd - 1, nd - 3, nd - 2)
+    return torch.empty(shape, dtype=dtype, device=x.device)
+
+
+def zoom2x_(x: torch.Tensor, out: torch.Tensor, params: Params | None = None, *, beta=2.0, k_eps=1e-8,
+            h=1.0, nbw=-1.0) -> torch.Tensor:
+    """One WD-WENO doubling of x into the caller's `out` (..., 2H, 2W)."""
+    p = _params(params, beta, k_eps, h, nbw)
+    s, d = _desc(x), _desc(out)
+    _lib.check(_lib.lib().weno_zoom2x(ctypes.byref(s), ctypes.byref(d), ctypes.byref(p), _stream(x.device)),
+               "weno_zoom2x")
+    return out
+
+
+def zoom2x(x: torch.Tensor, params: Params | None = None, *, out_dtype=None, beta=2.0, k_eps=1e-8, h=1.0,
+           nbw=-1.0) -> torch.Tensor:
+    """One WD-WENO doubling: (..., H, W) -> (..., 2H, 2W) in x's layout.
+
+    uint8 inputs are read on the [0,1] scale (value/255); `out_dtype` (default:
+    x's dtype) selects uint8 or float32 output."""
+    out = _empty_like_layout(x, 2, out_dtype or x.dtype)
+    return zoom2x_(x, out, params, beta=beta, k_eps=k_eps, h=h, nbw=nbw)
+
+
+class BatchedZoom:
+    """A planned batched call: the image table lives in a device workspace and
+    `run()` only enqueues kernels (capturable into a CUDA/HIP graph)."""
+
+    def __init__(self, xs, outs, params: Params | None = None):
+        if len(xs) != len(outs) or not xs:
+            raise ValueError("need equally many (>= 1) inputs and outputs")
+        self.xs, self.outs = list(xs), list(outs)
+        L = _lib.lib()
+        count = len(xs)
+        self._srcs = (WenoTensor * count)(*[_desc(t) for t in xs])
+        self._dsts = (WenoTensor * count)(*[_desc(t) for t in outs])
+        ws = L.weno_zoom2x_batched_workspace(count)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=xs[0].device)
+        self.plan = WenoBatchPlan()
+        p = (params or Params()).c()
+        _lib.check(
+            L.weno_zoom2x_batched_plan(self._srcs, self._dsts, count, ctypes.byref(p), self.workspace.data_ptr(), ws,
+                                       _stream(xs[0].device), ctypes.byref(self.plan)),
+            "weno_zoom2x_batched_plan",
+        )
+
+    def run(self):
+        _lib.check(_lib.lib().weno_zoom2x_batched_run(ctypes.byref(self.plan), _stream(self.xs[0].device)),
+                   "weno_zoom2x_batched_run")
+        return self.outs
+
+
+def zoom2x_batched(xs, params: Params | None = None, out_dtype=None):
+    """Zoom a list of images of uneven sizes in one persistent launch."""
+    outs = [_empty_like_layout(x, 2, out_dtype or x.dtype) for x in xs]
+    return BatchedZoom(xs, outs, params).run()
+
+
+def zoom2x_cascade(x: torch.Tensor, levels: int, params: Params | None = None, out_dtype=None,
+                   workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """`levels` successive doublings (eq. zoomfactor) with FP32 intermediates,
+    grid spacing halved per level."""
+    p = (params or Params()).c()
+    out = _empty_like_layout(x, 2 ** levels, out_dtype or x.dtype)
+    s, d = _desc(x), _desc(out)
+    L = _lib.lib()
+    ws = L.weno_zoom2x_cascade_workspace(ctypes.byref(s), int(levels))
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device=x.device)
+    _lib.check(L.weno_zoom2x_cascade(ctypes.byref(s), ctypes.byref(d), int(levels), ctypes.byref(p),
+                                     workspace.data_ptr(), workspace.numel(), _stream(x.device)),
+               "weno_zoom2x_cascade")
+    return out
+
+
+def cascade_workspace_bytes(x: torch.Tensor, levels: int) -> int:
+    s = _desc(x)
+    return int(_lib.lib().weno_zoom2x_cascade_workspace(ctypes.byref(s), int(levels)))
+
+
+def zoom2x_backward(x: torch.Tensor, grad_y: torch.Tensor, params: Params | None = None) -> torch.Tensor:
+    """Adjoint of zoom2x for float32 x: returns dL/dx given dL/dy."""
+    p = (params or Params()).c()
+    gx = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    a, g, o = _desc(x), _desc(grad_y), _desc(gx)
+    _lib.check(_lib.lib().weno_zoom2x_backward(ctypes.byref(a), ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),
+                                               _stream(x.device)), "weno_zoom2x_backward")
+    return gx
+
+
+class WenoZoom2x(torch.autograd.Function):
+    """Differentiable WD-WENO doubling of float32 (.., H, W) tensors."""
+
+    @staticmethod
+    def forward(ctx, x, params: Params | None = None):
+        params = params or Params()
+        ctx.params = params
+        ctx.save_for_backward(x)
+        return zoom2x(x, params)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        (x,) = ctx.saved_tensors
+        return zoom2x_backward(x, grad_y.contiguous(), ctx.params), None
+
+
+def set_launch_config(rows_per_strip: int, cols_per_lane: int):
+    _lib.check(_lib.lib().weno_set_launch_config(int(rows_per_strip), int(cols_per_lane)), "weno_set_launch_config")
+
+
+def get_launch_config():
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    _lib.lib().weno_get_launch_config(ctypes.byref(r), ctypes.byref(c))
+    return int(r.value), int(c.value)

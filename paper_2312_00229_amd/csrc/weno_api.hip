@@ -1,0 +1,532 @@
+// C ABI of the WD-WENO 2x zoom library (declarations and contracts in
+// include/weno_zoom.h).  Host-side validation, launch configuration and the
+// forward / batched / cascade kernels; the adjoint lives in weno_bwd.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "weno_zoom.h"
+#include "weno_fwd.h"
+#include "weno_internal.h"
+
+using namespace wz;
+
+// --------------------------------------------------------------------------
+// kernels
+// --------------------------------------------------------------------------
+namespace {
+
+template <int COLS, int BETA>
+__global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
+{
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int per_plane = jb.strips_x * jb.strips_y;
+    if (wave >= per_plane) return;  // whole wave
+    const int plane = blockIdx.y;
+    const int sy = wave / jb.strips_x;
+    const int sx = wave - sy * jb.strips_x;
+    StripCtx cx;
+    const int n = plane / jb.C, c = plane - n * jb.C;
+    cx.src_plane = jb.src + n * jb.s_n + c * jb.s_c;
+    cx.dst_plane = jb.dst + n * jb.d_n + c * jb.d_c;
+    cx.s_h = jb.s_h;
+    cx.s_w_bytes = (int32_t)jb.s_w;
+    cx.d_h = jb.d_h;
+    cx.d_w = jb.d_w;
+    cx.H = jb.H;
+    cx.W = jb.W;
+    cx.in_u8 = jb.in_u8;
+    cx.out_u8 = jb.out_u8;
+    cx.vec = jb.vec;
+    cx.out_scale = P.out_scale;
+    const int R0 = sy * rows_per_strip;
+    const int R1 = min(R0 + rows_per_strip, jb.H);
+    zoom_strip<COLS, BETA>(cx, P, sx, R0, R1);
+}
+
+// Persistent kernel over a work queue of strips of many images.  Item i of
+// image k covers plane (i / per_plane) and strip (i % per_plane); images are
+// stored in the table largest first, so the queue drains big items early.
+template <int COLS, int BETA>
+__global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable* tab, int rows_per_strip)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int count = tab->count;
+    const int64_t total = tab->total_items;
+    const FwdJob* jobs = batch_jobs(tab);
+    const int64_t* prefix = batch_prefix(tab);
+    unsigned long long* counter = &((BatchTable*)tab)->counter;
+    for (;;) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(counter, 1ull);
+        item = __shfl(item, 0);
+        if ((int64_t)item >= total) break;  // every wave reaches this exit
+        // image k with prefix[k] <= item < prefix[k+1]
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= (int64_t)item) lo = mid; else hi = mid - 1;
+        }
+        const FwdJob jb = jobs[lo];
+        const int64_t local = (int64_t)item - prefix[lo];
+        const int per_plane = jb.strips_x * jb.strips_y;
+        const int plane = (int)(local / per_plane);
+        const int wv = (int)(local - (int64_t)plane * per_plane);
+        const int sy = wv / jb.strips_x;
+        const int sx = wv - sy * jb.strips_x;
+        StripCtx cx;
+        const int n = plane / jb.C, c = plane - n * jb.C;
+        cx.src_plane = jb.src + n * jb.s_n + c * jb.s_c;
+        cx.dst_plane = jb.dst + n * jb.d_n + c * jb.d_c;
+        cx.s_h = jb.s_h;
+        cx.s_w_bytes = (int32_t)jb.s_w;
+        cx.d_h = jb.d_h;
+        cx.d_w = jb.d_w;
+        cx.H = jb.H;
+        cx.W = jb.W;
+        cx.in_u8 = jb.in_u8;
+        cx.out_u8 = jb.out_u8;
+        cx.vec = jb.vec;
+        const FwdParams P = batch_params(tab)[lo];
+        cx.out_scale = P.out_scale;
+        const int R0 = sy * rows_per_strip;
+        const int R1 = min(R0 + rows_per_strip, jb.H);
+        zoom_strip<COLS, BETA>(cx, P, sx, R0, R1);
+    }
+}
+
+__global__ void reset_counter_kernel(BatchTable* tab)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) tab->counter = 0ull;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// status / configuration
+// --------------------------------------------------------------------------
+static thread_local std::string g_status_text;
+static std::atomic<int32_t> g_rows_per_strip{64};
+static std::atomic<int32_t> g_cols_per_lane{2};
+
+int wz_hip_error(hipError_t e, const char* what)
+{
+    g_status_text = std::string(what) + ": " + hipGetErrorString(e);
+    return WENO_EHIP;
+}
+
+extern "C" const char* weno_status_string(int status)
+{
+    switch (status) {
+    case WENO_OK: return "ok";
+    case WENO_EINVAL: return "invalid argument (null pointer, size, shape or parameter)";
+    case WENO_EDTYPE: return "unsupported dtype combination";
+    case WENO_EOVERLAP: return "output overlaps an input";
+    case WENO_ENOSPC: return "workspace too small";
+    case WENO_EHIP:
+        if (g_status_text.empty()) return "HIP runtime error";
+        return g_status_text.c_str();
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char* weno_version(void) { return "1.0.0"; }
+
+extern "C" weno_params_t weno_default_params(void)
+{
+    weno_params_t p;
+    p.beta = 2.0f;
+    p.k_eps = 1e-8f;
+    p.h = 1.0f;
+    p.nbw = -1.0f;
+    return p;
+}
+
+extern "C" int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane)
+{
+    if (rows_per_strip < 8 || rows_per_strip > 1024 || rows_per_strip % 8 != 0) return WENO_EINVAL;
+    if (cols_per_lane != 1 && cols_per_lane != 2) return WENO_EINVAL;
+    g_rows_per_strip.store(rows_per_strip);
+    g_cols_per_lane.store(cols_per_lane);
+    return WENO_OK;
+}
+
+extern "C" void weno_get_launch_config(int32_t* rows_per_strip, int32_t* cols_per_lane)
+{
+    if (rows_per_strip) *rows_per_strip = g_rows_per_strip.load();
+    if (cols_per_lane) *cols_per_lane = g_cols_per_lane.load();
+}
+
+// --------------------------------------------------------------------------
+// validation helpers (shared with the adjoint and the cascade)
+// --------------------------------------------------------------------------
+int wz_esize(int32_t dtype) { return dtype == WENO_U8 ? 1 : (dtype == WENO_F32 ? 4 : 0); }
+
+int wz_check_tensor(const weno_tensor_t* t)
+{
+    if (!t || !t->data) return WENO_EINVAL;
+    if (wz_esize(t->dtype) == 0) return WENO_EDTYPE;
+    if (t->n < 1 || t->c < 1 || t->h < 1 || t->w < 1) return WENO_EINVAL;
+    if (t->sn < 0 || t->sc < 0 || t->sh < 0 || t->sw < 0) return WENO_EINVAL;
+    return WENO_OK;
+}
+
+void wz_byte_range(const weno_tensor_t* t, uintptr_t* lo, uintptr_t* hi)
+{
+    const int64_t es = wz_esize(t->dtype);
+    const int64_t last = ((int64_t)(t->n - 1) * t->sn + (int64_t)(t->c - 1) * t->sc + (int64_t)(t->h - 1) * t->sh +
+                          (int64_t)(t->w - 1) * t->sw) * es;
+    *lo = (uintptr_t)t->data;
+    *hi = (uintptr_t)t->data + (uintptr_t)last + (uintptr_t)es;
+}
+
+bool wz_overlap(const weno_tensor_t* a, const weno_tensor_t* b)
+{
+    uintptr_t alo, ahi, blo, bhi;
+    wz_byte_range(a, &alo, &ahi);
+    wz_byte_range(b, &blo, &bhi);
+    return alo < bhi && blo < ahi;
+}
+
+int wz_check_params(const weno_params_t* p)
+{
+    if (!p) return WENO_EINVAL;
+    if (!(p->beta >= 0.0f) || !std::isfinite(p->beta) || p->beta > 64.0f) return WENO_EINVAL;
+    if (!(p->k_eps >= 0.0f) || !std::isfinite(p->k_eps)) return WENO_EINVAL;
+    if (!(p->h > 0.0f) || !std::isfinite(p->h)) return WENO_EINVAL;
+    if (!std::isfinite(p->nbw)) return WENO_EINVAL;
+    const double eps = (double)p->k_eps * (double)p->h * (double)p->h;
+    // alpha = t^-beta must stay finite in FP32 for t >= eps
+    if (p->beta > 0.0f && (eps <= 0.0 || std::log2(eps) * (double)p->beta < -120.0)) return WENO_EINVAL;
+    return WENO_OK;
+}
+
+double wz_nbw(const weno_params_t* p) { return p->nbw < 0.0f ? (double)p->h * (double)p->h / 4.0 : (double)p->nbw; }
+
+FwdParams wz_fwd_params(const weno_params_t* p, int in_u8, int out_u8)
+{
+    const double w = wz_nbw(p);
+    const double vs = in_u8 ? 255.0 : 1.0;  // kernel value scale relative to [0,1]
+    const double eps = (double)p->k_eps * (double)p->h * (double)p->h * vs * vs;
+    FwdParams P;
+    P.eps_hat = (float)(eps * (12.0 / 13.0) / (1.0 + 4.0 * w));
+    P.w = (float)w;
+    P.beta = p->beta;
+    const double os = out_u8 ? 255.0 : 1.0;
+    P.out_scale = (float)(os / vs);
+    return P;
+}
+
+int wz_beta_mode(float beta)
+{
+    if (beta == 2.0f) return 2;
+    if (beta == 1.0f) return 1;
+    return kBetaGeneral;
+}
+
+// Fill a FwdJob for src -> dst (shapes already validated).
+FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols, int rows_per_strip)
+{
+    FwdJob jb;
+    const int64_t ei = wz_esize(src->dtype), eo = wz_esize(dst->dtype);
+    jb.src = (const uint8_t*)src->data;
+    jb.dst = (uint8_t*)dst->data;
+    jb.H = src->h;
+    jb.W = src->w;
+    jb.C = src->c;
+    jb.planes = src->n * src->c;
+    jb.s_n = src->sn * ei;
+    jb.s_c = src->sc * ei;
+    jb.s_h = src->sh * ei;
+    jb.s_w = src->sw * ei;
+    jb.d_n = dst->sn * eo;
+    jb.d_c = dst->sc * eo;
+    jb.d_h = dst->sh * eo;
+    jb.d_w = dst->sw * eo;
+    jb.in_u8 = src->dtype == WENO_U8;
+    jb.out_u8 = dst->dtype == WENO_U8;
+    const int own = cols == 1 ? kWave - 9 : 2 * kWave - 10;
+    jb.strips_x = (src->w + own - 1) / own;
+    jb.strips_y = (src->h + rows_per_strip - 1) / rows_per_strip;
+    // vector stores need contiguous rows and aligned plane/row starts
+    const uintptr_t base = (uintptr_t)dst->data;
+    int vec = 0;
+    if (!jb.out_u8 && dst->sw == 1) {
+        const bool a8 = base % 8 == 0 && (jb.d_h % 8 == 0) && (jb.d_n % 8 == 0) && (jb.d_c % 8 == 0);
+        const bool a16 = base % 16 == 0 && (jb.d_h % 16 == 0) && (jb.d_n % 16 == 0) && (jb.d_c % 16 == 0);
+        vec = a16 ? 2 : (a8 ? 1 : 0);
+    }
+    jb.vec = vec;
+    jb.pad_ = 0;
+    return jb;
+}
+
+// shape rules of one doubling
+int wz_check_pair(const weno_tensor_t* src, const weno_tensor_t* dst, int factor)
+{
+    int rc = wz_check_tensor(src);
+    if (rc) return rc;
+    rc = wz_check_tensor(dst);
+    if (rc) return rc;
+    if (dst->n != src->n || dst->c != src->c) return WENO_EINVAL;
+    if ((int64_t)dst->h != (int64_t)src->h * factor || (int64_t)dst->w != (int64_t)src->w * factor) return WENO_EINVAL;
+    if ((int64_t)src->n * src->c > 65535) return WENO_EINVAL;
+    // per-lane column offsets are 32-bit
+    if ((int64_t)src->w * src->sw * wz_esize(src->dtype) >= (1ll << 31)) return WENO_EINVAL;
+    if ((int64_t)dst->w * dst->sw * wz_esize(dst->dtype) >= (1ll << 31)) return WENO_EINVAL;
+    if (wz_overlap(src, dst)) return WENO_EOVERLAP;
+    return WENO_OK;
+}
+
+template <int COLS>
+static hipError_t launch_fwd_cols(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
+{
+    const int per_plane = jb.strips_x * jb.strips_y;
+    dim3 grid((per_plane + kWavesPerBlock - 1) / kWavesPerBlock, jb.planes);
+    dim3 block(kBlock);
+    if (beta_mode == 2)
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, 2>), grid, block, 0, st, jb, P, rows);
+    else if (beta_mode == 1)
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, 1>), grid, block, 0, st, jb, P, rows);
+    else
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, kBetaGeneral>), grid, block, 0, st, jb, P, rows);
+    return hipGetLastError();
+}
+
+int wz_launch_fwd(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, hipStream_t st,
+                  int rows, int cols)
+{
+    const FwdJob jb = wz_make_job(src, dst, cols, rows);
+    const FwdParams P = wz_fwd_params(p, jb.in_u8, jb.out_u8);
+    const int bm = wz_beta_mode(p->beta);
+    const hipError_t e = cols == 1 ? launch_fwd_cols<1>(jb, P, bm, rows, st) : launch_fwd_cols<2>(jb, P, bm, rows, st);
+    if (e != hipSuccess) return wz_hip_error(e, "zoom2x_kernel launch");
+    return WENO_OK;
+}
+
+// --------------------------------------------------------------------------
+// single doubling
+// --------------------------------------------------------------------------
+extern "C" int weno_zoom2x(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p,
+                           void* hip_stream)
+{
+    int rc = wz_check_pair(src, dst, 2);
+    if (rc) return rc;
+    rc = wz_check_params(p);
+    if (rc) return rc;
+    return wz_launch_fwd(src, dst, p, (hipStream_t)hip_stream, g_rows_per_strip.load(), g_cols_per_lane.load());
+}
+
+// --------------------------------------------------------------------------
+// batched
+// --------------------------------------------------------------------------
+extern "C" size_t weno_zoom2x_batched_workspace(int32_t count)
+{
+    if (count < 1) return 0;
+    return batch_table_bytes(count);
+}
+
+extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count,
+                                        const weno_params_t* p, void* d_workspace, size_t ws_bytes,
+                                        void* hip_stream, weno_batch_plan_t* plan)
+{
+    if (!srcs || !dsts || !plan || count < 1 || !d_workspace) return WENO_EINVAL;
+    int rc = wz_check_params(p);
+    if (rc) return rc;
+    if ((uintptr_t)d_workspace % 256 != 0) return WENO_EINVAL;
+    if (ws_bytes < batch_table_bytes(count)) return WENO_ENOSPC;
+    for (int i = 0; i < count; ++i) {
+        rc = wz_check_pair(&srcs[i], &dsts[i], 2);
+        if (rc) return rc;
+    }
+    // no output may overlap any input or another output: sweep all byte
+    // ranges by start address, remembering the furthest end of each kind
+    {
+        struct Iv { uintptr_t lo, hi; bool out; };
+        std::vector<Iv> iv(2 * (size_t)count);
+        for (int i = 0; i < count; ++i) {
+            wz_byte_range(&srcs[i], &iv[2 * i].lo, &iv[2 * i].hi);
+            iv[2 * i].out = false;
+            wz_byte_range(&dsts[i], &iv[2 * i + 1].lo, &iv[2 * i + 1].hi);
+            iv[2 * i + 1].out = true;
+        }
+        std::sort(iv.begin(), iv.end(), [](const Iv& a, const Iv& b) { return a.lo < b.lo; });
+        uintptr_t end_in = 0, end_out = 0;
+        for (const Iv& v : iv) {
+            if (v.lo < end_out || (v.out && v.lo < end_in)) return WENO_EOVERLAP;
+            if (v.out) end_out = std::max(end_out, v.hi); else end_in = std::max(end_in, v.hi);
+        }
+    }
+    const int rows = g_rows_per_strip.load(), cols = g_cols_per_lane.load();
+    // largest images first
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)srcs[a].h * srcs[a].w * srcs[a].n * srcs[a].c >
+               (int64_t)srcs[b].h * srcs[b].w * srcs[b].n * srcs[b].c;
+    });
+    std::vector<uint8_t> host(batch_table_bytes(count), 0);
+    BatchTable* tab = (BatchTable*)host.data();
+    FwdJob* jobs = (FwdJob*)(host.data() + batch_jobs_offset());
+    int64_t* prefix = (int64_t*)(host.data() + batch_prefix_offset(count));
+    FwdParams* prm = (FwdParams*)(host.data() + batch_params_offset(count));
+    int64_t total = 0;
+    for (int k = 0; k < count; ++k) {
+        const int i = order[k];
+        jobs[k] = wz_make_job(&srcs[i], &dsts[i], cols, rows);
+        prm[k] = wz_fwd_params(p, jobs[k].in_u8, jobs[k].out_u8);
+        prefix[k] = total;
+        total += (int64_t)jobs[k].planes * jobs[k].strips_x * jobs[k].strips_y;
+    }
+    prefix[count] = total;
+    tab->count = count;
+    tab->total_items = total;
+    tab->counter = 0;
+    tab->params_offset = batch_params_offset(count);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(d_workspace, host.data(), host.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return wz_hip_error(e, "batch table copy");
+    e = hipStreamSynchronize(st);  // the host table is freed on return
+    if (e != hipSuccess) return wz_hip_error(e, "batch table copy");
+    plan->d_workspace = d_workspace;
+    plan->ws_bytes = ws_bytes;
+    plan->total_items = total;
+    plan->count = count;
+    plan->rows_per_strip = rows;
+    plan->cols_per_lane = cols;
+    plan->beta_mode = wz_beta_mode(p->beta);
+    plan->reserved = 0;
+    return WENO_OK;
+}
+
+template <int COLS>
+static hipError_t launch_batched_cols(const weno_batch_plan_t* plan, hipStream_t st)
+{
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+    const int64_t waves_needed = plan->total_items;
+    int64_t blocks = (int64_t)cus * 4;  // up to 4 workgroups (16 waves) per CU
+    const int64_t by_work = (waves_needed + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > by_work) blocks = by_work;
+    if (blocks < 1) blocks = 1;
+    const BatchTable* tab = (const BatchTable*)plan->d_workspace;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, (BatchTable*)plan->d_workspace);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (plan->beta_mode == 2)
+        hipLaunchKernelGGL((zoom2x_batched_kernel<COLS, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tab,
+                           plan->rows_per_strip);
+    else if (plan->beta_mode == 1)
+        hipLaunchKernelGGL((zoom2x_batched_kernel<COLS, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tab,
+                           plan->rows_per_strip);
+    else
+        hipLaunchKernelGGL((zoom2x_batched_kernel<COLS, kBetaGeneral>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                           tab, plan->rows_per_strip);
+    return hipGetLastError();
+}
+
+extern "C" int weno_zoom2x_batched_run(const weno_batch_plan_t* plan, void* hip_stream)
+{
+    if (!plan || !plan->d_workspace || plan->count < 1 || plan->total_items < 1) return WENO_EINVAL;
+    if (plan->cols_per_lane != 1 && plan->cols_per_lane != 2) return WENO_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const hipError_t e = plan->cols_per_lane == 1 ? launch_batched_cols<1>(plan, st) : launch_batched_cols<2>(plan, st);
+    if (e != hipSuccess) return wz_hip_error(e, "zoom2x_batched_kernel launch");
+    return WENO_OK;
+}
+
+extern "C" int weno_zoom2x_batched(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count,
+                                   const weno_params_t* p, void* d_workspace, size_t ws_bytes, void* hip_stream)
+{
+    weno_batch_plan_t plan;
+    int rc = weno_zoom2x_batched_plan(srcs, dsts, count, p, d_workspace, ws_bytes, hip_stream, &plan);
+    if (rc) return rc;
+    return weno_zoom2x_batched_run(&plan, hip_stream);
+}
+
+// --------------------------------------------------------------------------
+// cascade of doublings
+// --------------------------------------------------------------------------
+static void cascade_level_shape(const weno_tensor_t* src, int lvl, int64_t* h, int64_t* w)
+{
+    *h = (int64_t)src->h << lvl;
+    *w = (int64_t)src->w << lvl;
+}
+
+extern "C" size_t weno_zoom2x_cascade_workspace(const weno_tensor_t* src, int32_t levels)
+{
+    if (wz_check_tensor(src) != WENO_OK || levels < 1 || levels > 8) return 0;
+    size_t total = 0;
+    for (int l = 1; l < levels; ++l) {
+        int64_t h, w;
+        cascade_level_shape(src, l, &h, &w);
+        const size_t bytes = (size_t)src->n * src->c * h * w * 4;
+        total += (bytes + 255) / 256 * 256;
+    }
+    return total == 0 ? 256 : total;
+}
+
+extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t* dst, int32_t levels,
+                                   const weno_params_t* p, void* d_workspace, size_t ws_bytes, void* hip_stream)
+{
+    if (levels < 1 || levels > 8) return WENO_EINVAL;
+    int rc = wz_check_tensor(src);
+    if (rc) return rc;
+    rc = wz_check_tensor(dst);
+    if (rc) return rc;
+    rc = wz_check_params(p);
+    if (rc) return rc;
+    if (dst->n != src->n || dst->c != src->c || (int64_t)dst->h != ((int64_t)src->h << levels) ||
+        (int64_t)dst->w != ((int64_t)src->w << levels))
+        return WENO_EINVAL;
+    if (wz_overlap(src, dst)) return WENO_EOVERLAP;
+    if (levels > 1) {
+        if (!d_workspace) return WENO_EINVAL;
+        if (ws_bytes < weno_zoom2x_cascade_workspace(src, levels)) return WENO_ENOSPC;
+    }
+    const int rows = g_rows_per_strip.load(), cols = g_cols_per_lane.load();
+    weno_tensor_t cur = *src;
+    size_t off = 0;
+    weno_params_t lp = *p;
+    const double w0 = wz_nbw(p);
+    for (int l = 0; l < levels; ++l) {
+        weno_tensor_t out;
+        if (l == levels - 1) {
+            out = *dst;
+        } else {
+            int64_t h, w;
+            cascade_level_shape(src, l + 1, &h, &w);
+            out.data = (uint8_t*)d_workspace + off;
+            out.dtype = WENO_F32;
+            out.n = src->n;
+            out.c = src->c;
+            out.h = (int32_t)h;
+            out.w = (int32_t)w;
+            out.sw = 1;
+            out.sh = w;
+            out.sc = h * w;
+            out.sn = (int64_t)src->c * h * w;
+            const size_t bytes = (size_t)src->n * src->c * h * w * 4;
+            off += (bytes + 255) / 256 * 256;
+            if (wz_overlap(&out, dst) || wz_overlap(&out, src)) return WENO_EOVERLAP;
+        }
+        rc = wz_check_pair(&cur, &out, 2);
+        if (rc) return rc;
+        // level l works on spacing h / 2^l; an explicit neighbour weight scales with h^2
+        const double scale = std::ldexp(1.0, -l);
+        lp.h = (float)(p->h * scale);
+        lp.nbw = (float)(w0 * scale * scale);
+        rc = wz_launch_fwd(&cur, &out, &lp, (hipStream_t)hip_stream, rows, cols);
+        if (rc) return rc;
+        cur = out;
+    }
+    return WENO_OK;
+}

@@ -1,0 +1,413 @@
+// Forward WD-WENO 2x kernel body for gfx950 (CDNA4, wave64).
+//
+// Method: arXiv 2312.00229, Section 3 -- phase 1 (x points, diagonal
+// candidates, eqs. Vektor, p, 2Dsmoothness, 2DsmoothnessFinal, alpha,
+// IzrazOmega2d, 2dKombinacija) and phase 2 (+ points, axis candidates,
+// eqs. tezine, IzrazOmega2dRavno, 2dKombinacijaRavno), fused per output quad.
+//
+// Work decomposition ("strip walk"): one wave owns a strip of 64*COLS
+// consecutive input columns and walks down `rows` input rows.  Lane l holds
+// columns Jbase + l*COLS + c (c < COLS); left/right neighbours come from the
+// adjacent lane through wave-wide DPP shifts, which the compiler folds into
+// the consuming ALU op, so no LDS is needed.  Vertical neighbours live in
+// register windows that slide one row per iteration.  The first 4 and the
+// last 5..6 columns of a strip are halo (a quad reads columns J-4..J+5); the
+// strip walk starts 9 rows above its first output row to fill the pipeline.
+//
+// Per iteration R (output quad row R) the stages are, in dependency order:
+//   load   V(R+5)
+//   dd     diagonal second differences at input row R+4
+//   sx     phase-1 candidates p and indicators SI of x points at row R+3
+//   x      D = SI + w * (4 neighbours) and the blend for x points at row R+2
+//   p2     phase-2 candidates/indicators of the + points B(R+1,.) and A(R,.)
+//   blend  A(R,.), B(R,.), then the 2x2 quad store of row R.
+//
+// Arithmetic (all FP32): for a stencil (a, b, c) on nodes -1, 1, 3 the
+// candidate is (a+b)/2 - dd/8 with dd = a - 2b + c, and the indicator
+// (b-a)^2 + 13/12 dd^2.  The kernel carries SI' = (12/13) SI: the common
+// factor cancels in the normalised weights.  eps is folded into every SI' as
+// eps_hat = eps*12/13 / (1 + 4w), so SI'_self + w * sum SI'_nbr = (12/13)(D + eps).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wz {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+// beta specialisations
+constexpr int kBetaGeneral = -1;
+
+struct FwdParams {
+    float eps_hat;  // see header comment, in the kernel's value scale
+    float w;        // neighbour-indicator weight
+    float beta;     // used by the general-beta path
+    float out_scale;  // output value = u * out_scale before quantisation
+};
+
+// One image (all of its planes) for the forward kernels.
+struct FwdJob {
+    const uint8_t* src;  // byte pointer to element 0
+    uint8_t* dst;
+    int32_t H, W, C, planes;          // planes = N * C
+    int64_t s_n, s_c, s_h, s_w;       // byte strides of the source
+    int64_t d_n, d_c, d_h, d_w;       // byte strides of the destination
+    int32_t in_u8, out_u8;            // element types
+    int32_t strips_x, strips_y;       // strips per plane
+    int32_t vec;                      // 2: float4 rows, 1: float2 rows, 0: scalar stores
+    int32_t pad_;
+};
+
+__device__ __forceinline__ float from_left(float x)
+{   // lane i receives lane i-1 (wave_shr:1); lane 0 receives 0
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_right(float x)
+{   // lane i receives lane i+1 (wave_shl:1); lane 63 receives 0
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, true));
+}
+
+// value of column (c - 1) / (c + 1) of a per-lane column array
+template <int COLS>
+__device__ __forceinline__ float lft(const float (&x)[COLS], int c)
+{
+    return c > 0 ? x[c - 1] : from_left(x[COLS - 1]);
+}
+template <int COLS>
+__device__ __forceinline__ float rgt(const float (&x)[COLS], int c)
+{
+    return c < COLS - 1 ? x[c + 1] : from_right(x[0]);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// alpha_k = 0.5 / t_k^beta (the 0.5 cancels), u = sum alpha_k p_k / sum alpha_k
+template <int BETA>
+__device__ __forceinline__ float blend4(float t0, float t1, float t2, float t3,
+                                        float p0, float p1, float p2, float p3, float beta)
+{
+    float a0, a1, a2, a3;
+    if constexpr (BETA == 2) {
+        float r0 = rcp(t0), r1 = rcp(t1), r2 = rcp(t2), r3 = rcp(t3);
+        a0 = r0 * r0; a1 = r1 * r1; a2 = r2 * r2; a3 = r3 * r3;
+    } else if constexpr (BETA == 1) {
+        a0 = rcp(t0); a1 = rcp(t1); a2 = rcp(t2); a3 = rcp(t3);
+    } else {
+        a0 = __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(t0));
+        a1 = __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(t1));
+        a2 = __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(t2));
+        a3 = __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(t3));
+    }
+    float S = (a0 + a1) + (a2 + a3);
+    float N = __builtin_fmaf(a3, p3, __builtin_fmaf(a2, p2, __builtin_fmaf(a1, p1, a0 * p0)));
+    return N * rcp(S);
+}
+
+// candidate (a+b)/2 - dd/8 given m = (a+b)/2, and the scaled indicator
+__device__ __forceinline__ float cand(float dd, float m) { return __builtin_fmaf(dd, -0.125f, m); }
+__device__ __forceinline__ float sidx(float dd, float gc) { return __builtin_fmaf(dd, dd, gc); }
+// g^2 * 12/13 + eps_hat
+__device__ __forceinline__ float gterm(float g, float eps_hat) { return __builtin_fmaf(g * g, 12.0f / 13.0f, eps_hat); }
+// a - 2b + c
+__device__ __forceinline__ float d2(float a, float b, float c) { return __builtin_fmaf(-2.0f, b, a + c); }
+
+template <int COLS>
+struct StripState {
+    // input rows R .. R+4 (row R+5 is loaded by the iteration)
+    float V0[COLS], V1[COLS], V2[COLS], V3[COLS], V4[COLS];
+    // main-diagonal second difference centred at (R+3, J); anti-diagonal at (R+3, J+1)
+    float dd1_3[COLS], dd2s_3[COLS];
+    // phase-1 scaled indicators at x rows R+1, R+2 and candidates at x row R+2
+    float SX1[4][COLS], SX2[4][COLS], PX2[4][COLS];
+    // x values at rows R, R+1
+    float X0[COLS], X1[COLS];
+    // vertical second differences centred at row R: of x (X(R-1)-2X(R)+X(R+1)) and of V
+    float ddXv0[COLS], ddr0[COLS];
+    // phase-2: B(R) indicators/candidates, B pair sums at row R, A pair sums at row R-1
+    float SB0[4][COLS], PB0[4][COLS], hB0[4][COLS], hAm1[4][COLS];
+};
+
+struct StripCtx {
+    const uint8_t* src_plane;
+    uint8_t* dst_plane;
+    int64_t s_h, d_h, d_w;
+    int32_t s_w_bytes;
+    int32_t H, W;
+    int32_t in_u8, out_u8, vec;
+    float out_scale;
+};
+
+template <int COLS>
+__device__ __forceinline__ void load_row(const StripCtx& cx, const uint32_t (&off)[COLS], int r, float (&v)[COLS])
+{
+    int rc = r < 0 ? 0 : (r >= cx.H ? cx.H - 1 : r);
+    const uint8_t* rowp = cx.src_plane + (int64_t)rc * cx.s_h;
+    if (cx.in_u8) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) v[c] = (float)rowp[off[c]];
+    } else {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) v[c] = *(const float*)(rowp + off[c]);
+    }
+}
+
+__device__ __forceinline__ uint32_t quant_u8(float u)
+{
+    float q = __builtin_rintf(u);
+    q = __builtin_fminf(__builtin_fmaxf(q, 0.0f), 255.0f);
+    return (uint32_t)q;
+}
+
+// store the 2x2 quads of row R for this lane's columns
+template <int COLS>
+__device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int (&J)[COLS], bool own_all,
+                                            const bool (&own)[COLS], const float (&o00)[COLS],
+                                            const float (&o01)[COLS], const float (&o10)[COLS],
+                                            const float (&o11)[COLS])
+{
+    uint8_t* r0 = cx.dst_plane + (int64_t)(2 * R) * cx.d_h;
+    uint8_t* r1 = r0 + cx.d_h;
+    if (!cx.out_u8) {
+        const float s = cx.out_scale;
+        if (COLS == 2 && cx.vec == 2 && own_all) {
+            uint32_t off = (uint32_t)(2 * J[0]) * 4u;
+            *(float4*)(r0 + off) = make_float4(o00[0] * s, o01[0] * s, o00[COLS - 1] * s, o01[COLS - 1] * s);
+            *(float4*)(r1 + off) = make_float4(o10[0] * s, o11[0] * s, o10[COLS - 1] * s, o11[COLS - 1] * s);
+        } else if (cx.vec >= 1) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                if (!own[c]) continue;
+                uint32_t off = (uint32_t)(2 * J[c]) * 4u;
+                *(float2*)(r0 + off) = make_float2(o00[c] * s, o01[c] * s);
+                *(float2*)(r1 + off) = make_float2(o10[c] * s, o11[c] * s);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                if (!own[c]) continue;
+                int64_t off0 = (int64_t)(2 * J[c]) * cx.d_w;
+                *(float*)(r0 + off0) = o00[c] * s;
+                *(float*)(r0 + off0 + cx.d_w) = o01[c] * s;
+                *(float*)(r1 + off0) = o10[c] * s;
+                *(float*)(r1 + off0 + cx.d_w) = o11[c] * s;
+            }
+        }
+    } else {
+        const float s = cx.out_scale;
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            if (!own[c]) continue;
+            int64_t off0 = (int64_t)(2 * J[c]) * cx.d_w;
+            r0[off0] = (uint8_t)quant_u8(o00[c] * s);
+            r0[off0 + cx.d_w] = (uint8_t)quant_u8(o01[c] * s);
+            r1[off0] = (uint8_t)quant_u8(o10[c] * s);
+            r1[off0 + cx.d_w] = (uint8_t)quant_u8(o11[c] * s);
+        }
+    }
+}
+
+// One strip-walk iteration.  FULL = main loop (every stage runs, quad row R
+// is stored); otherwise a prologue iteration, d = R - R0 < 0, and each
+// stage only runs once its results can feed an output row >= R0.
+template <int COLS, int BETA, bool FULL>
+__device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& cx, const FwdParams& P,
+                                           const uint32_t (&off)[COLS], const int (&J)[COLS],
+                                           bool own_all, const bool (&own)[COLS], int R, int d)
+{
+    const bool do_dd = FULL || d >= -7;
+    const bool do_sx = FULL || d >= -6;
+    const bool do_x = FULL || d >= -4;
+    const bool do_p2dd = FULL || d >= -2;
+    const bool do_p2 = FULL || d >= -1;
+    const float eh = P.eps_hat, w = P.w;
+
+    float V5[COLS];
+    load_row<COLS>(cx, off, R + 5, V5);
+
+    // ---- dd: diagonal second differences centred at (R+4, J) ----
+    float dd1_4[COLS] = {}, dd2_4[COLS] = {}, dd1s_4[COLS] = {}, dd2s_4[COLS] = {};
+    if (do_dd) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            dd1_4[c] = d2(lft(s.V3, c), s.V4[c], rgt(V5, c));  // (R+3,J-1) (R+4,J) (R+5,J+1)
+            dd2_4[c] = d2(rgt(s.V3, c), s.V4[c], lft(V5, c));  // (R+3,J+1) (R+4,J) (R+5,J-1)
+        }
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            dd1s_4[c] = rgt(dd1_4, c);
+            dd2s_4[c] = rgt(dd2_4, c);
+        }
+    }
+
+    // ---- sx: phase-1 candidates and indicators of X(R+3, J) ----
+    // X(R+3,J) sits at (R+3.5, J+0.5).  Main diagonal line through V(R+3,J),
+    // V(R+4,J+1): k0 steps (+1,+1) (dd centred at (R+4,J+1)), k2 steps (-1,-1)
+    // (dd centred at (R+3,J)).  Anti-diagonal line through V(R+3,J+1), V(R+4,J):
+    // k1 steps (-1,+1) (dd centred at (R+3,J+1)), k3 steps (+1,-1) (dd at (R+4,J)).
+    float SX3[4][COLS] = {}, PX3[4][COLS] = {};
+    if (do_sx) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            const float a1 = s.V3[c], b1 = rgt(s.V4, c);
+            const float a2 = rgt(s.V3, c), b2 = s.V4[c];
+            const float gc1 = gterm(b1 - a1, eh), gc2 = gterm(b2 - a2, eh);
+            const float m1 = 0.5f * (a1 + b1), m2 = 0.5f * (a2 + b2);
+            SX3[0][c] = sidx(dd1s_4[c], gc1);   PX3[0][c] = cand(dd1s_4[c], m1);
+            SX3[2][c] = sidx(s.dd1_3[c], gc1);  PX3[2][c] = cand(s.dd1_3[c], m1);
+            SX3[1][c] = sidx(s.dd2s_3[c], gc2); PX3[1][c] = cand(s.dd2s_3[c], m2);
+            SX3[3][c] = sidx(dd2_4[c], gc2);    PX3[3][c] = cand(dd2_4[c], m2);
+        }
+    }
+
+    // ---- x: D over the four same-direction neighbours (I+-1, J), (I, J+-1); blend X(R+2, J) ----
+    float X2[COLS] = {};
+    if (do_x) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            float t[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float ns = (s.SX1[k][c] + SX3[k][c]) + (lft(s.SX2[k], c) + rgt(s.SX2[k], c));
+                t[k] = __builtin_fmaf(w, ns, s.SX2[k][c]);
+            }
+            X2[c] = blend4<BETA>(t[0], t[1], t[2], t[3], s.PX2[0][c], s.PX2[1][c], s.PX2[2][c], s.PX2[3][c], P.beta);
+        }
+    }
+
+    // ---- vertical second differences centred at row R+1 ----
+    float ddXv1[COLS] = {}, ddr1[COLS] = {};
+    if (do_p2dd) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            ddXv1[c] = d2(s.X0[c], s.X1[c], X2[c]);
+            ddr1[c] = d2(s.V0[c], s.V1[c], s.V2[c]);
+        }
+    }
+
+    // ---- p2: + points.  Directions k0 (+1,0) down, k1 (0,+1) right, k2 up, k3 left ----
+    float SB1[4][COLS] = {}, PB1[4][COLS] = {}, hB1[4][COLS] = {};
+    float SA0[4][COLS] = {}, PA0[4][COLS] = {}, hA0[4][COLS] = {};
+    if (do_p2) {
+        float v1r[COLS], ddc[COLS], x0l[COLS], ddXh[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            v1r[c] = rgt(s.V1, c);
+            ddc[c] = d2(lft(s.V1, c), s.V1[c], v1r[c]);     // V row R+1, centred at J
+            x0l[c] = lft(s.X0, c);
+            ddXh[c] = d2(x0l[c], s.X0[c], rgt(s.X0, c));    // X row R, centred at J
+        }
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            // B(R+1, J) at (R+1, J+1/2).  Vertical line through X(R,J), X(R+1,J):
+            const float gcv = gterm(s.X1[c] - s.X0[c], eh), mv = 0.5f * (s.X0[c] + s.X1[c]);
+            SB1[0][c] = sidx(ddXv1[c], gcv);   PB1[0][c] = cand(ddXv1[c], mv);    // X(R), X(R+1), X(R+2)
+            SB1[2][c] = sidx(s.ddXv0[c], gcv); PB1[2][c] = cand(s.ddXv0[c], mv);  // X(R+1), X(R), X(R-1)
+            // horizontal line through V(R+1,J), V(R+1,J+1)
+            const float gch = gterm(v1r[c] - s.V1[c], eh), mh = 0.5f * (s.V1[c] + v1r[c]);
+            const float ddcs = rgt(ddc, c);                                        // centred at J+1
+            SB1[1][c] = sidx(ddcs, gch);       PB1[1][c] = cand(ddcs, mh);        // V(R+1,J..J+2)
+            SB1[3][c] = sidx(ddc[c], gch);     PB1[3][c] = cand(ddc[c], mh);      // V(R+1,J+1..J-1)
+
+            // A(R, J) at (R+1/2, J).  Vertical line through V(R,J), V(R+1,J):
+            const float gav = gterm(s.V1[c] - s.V0[c], eh), mav = 0.5f * (s.V0[c] + s.V1[c]);
+            SA0[0][c] = sidx(ddr1[c], gav);    PA0[0][c] = cand(ddr1[c], mav);    // V(R), V(R+1), V(R+2)
+            SA0[2][c] = sidx(s.ddr0[c], gav);  PA0[2][c] = cand(s.ddr0[c], mav);  // V(R+1), V(R), V(R-1)
+            // horizontal line through X(R,J-1), X(R,J)
+            const float gah = gterm(s.X0[c] - x0l[c], eh), mah = 0.5f * (x0l[c] + s.X0[c]);
+            const float ddXhl = lft(ddXh, c);                                      // centred at J-1
+            SA0[1][c] = sidx(ddXh[c], gah);    PA0[1][c] = cand(ddXh[c], mah);    // X(R,J-1..J+1)
+            SA0[3][c] = sidx(ddXhl, gah);      PA0[3][c] = cand(ddXhl, mah);      // X(R,J..J-2)
+        }
+        // pair sums for the combined indicators of eq. (tezine):
+        //   D_A(I,J) = SI_A(I,J) + w [SI_B(I,J-1) + SI_B(I,J) + SI_B(I+1,J-1) + SI_B(I+1,J)]
+        //   D_B(I,J) = SI_B(I,J) + w [SI_A(I-1,J) + SI_A(I-1,J+1) + SI_A(I,J) + SI_A(I,J+1)]
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                hB1[k][c] = lft(SB1[k], c) + SB1[k][c];
+                hA0[k][c] = SA0[k][c] + rgt(SA0[k], c);
+            }
+        }
+    }
+
+    // ---- blend A(R, .), B(R, .) and store quad row R ----
+    if (FULL) {
+        float Aq[COLS], Bq[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            float ta[4], tb[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ta[k] = __builtin_fmaf(w, s.hB0[k][c] + hB1[k][c], SA0[k][c]);
+                tb[k] = __builtin_fmaf(w, s.hAm1[k][c] + hA0[k][c], s.SB0[k][c]);
+            }
+            Aq[c] = blend4<BETA>(ta[0], ta[1], ta[2], ta[3], PA0[0][c], PA0[1][c], PA0[2][c], PA0[3][c], P.beta);
+            Bq[c] = blend4<BETA>(tb[0], tb[1], tb[2], tb[3], s.PB0[0][c], s.PB0[1][c], s.PB0[2][c],
+                                 s.PB0[3][c], P.beta);
+        }
+        store_quads<COLS>(cx, R, J, own_all, own, s.V0, Bq, Aq, s.X0);
+    }
+
+    // ---- slide the windows by one row ----
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        s.V0[c] = s.V1[c]; s.V1[c] = s.V2[c]; s.V2[c] = s.V3[c]; s.V3[c] = s.V4[c]; s.V4[c] = V5[c];
+        s.dd1_3[c] = dd1_4[c]; s.dd2s_3[c] = dd2s_4[c];
+        s.X0[c] = s.X1[c]; s.X1[c] = X2[c];
+        s.ddXv0[c] = ddXv1[c]; s.ddr0[c] = ddr1[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s.SX1[k][c] = s.SX2[k][c]; s.SX2[k][c] = SX3[k][c]; s.PX2[k][c] = PX3[k][c];
+            s.SB0[k][c] = SB1[k][c]; s.PB0[k][c] = PB1[k][c]; s.hB0[k][c] = hB1[k][c];
+            s.hAm1[k][c] = hA0[k][c];
+        }
+    }
+}
+
+// Walk one strip: columns [Jbase, Jbase + 64*COLS), output rows [R0, R1).
+template <int COLS, int BETA>
+__device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
+{
+    constexpr int SPAN = kWave * COLS;
+    constexpr int HALO_L = 4;
+    constexpr int OWN = (COLS == 1) ? SPAN - 9 : SPAN - 10;  // even for COLS = 2 (16-byte stores)
+    const int lane = threadIdx.x & (kWave - 1);
+    const int Jbase = strip_x * OWN - HALO_L;
+    int J[COLS];
+    bool own[COLS];
+    uint32_t off[COLS];
+    bool own_all = true;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        const int sidx_ = lane * COLS + c;
+        J[c] = Jbase + sidx_;
+        own[c] = (sidx_ >= HALO_L) && (sidx_ < HALO_L + OWN) && (J[c] < cx.W);
+        own_all = own_all && own[c];
+        const int jc = J[c] < 0 ? 0 : (J[c] >= cx.W ? cx.W - 1 : J[c]);
+        off[c] = (uint32_t)jc * (uint32_t)cx.s_w_bytes;
+    }
+
+    StripState<COLS> s;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        s.V0[c] = s.V1[c] = s.V2[c] = s.V3[c] = s.V4[c] = 0.0f;
+        s.dd1_3[c] = s.dd2s_3[c] = s.X0[c] = s.X1[c] = s.ddXv0[c] = s.ddr0[c] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s.SX1[k][c] = s.SX2[k][c] = s.PX2[k][c] = 0.0f;
+            s.SB0[k][c] = s.PB0[k][c] = s.hB0[k][c] = s.hAm1[k][c] = 0.0f;
+        }
+    }
+
+    // prologue: rows R0-9 .. R0-1 fill the pipeline (no stores)
+    for (int d = -9; d < 0; ++d) strip_step<COLS, BETA, false>(s, cx, P, off, J, own_all, own, R0 + d, d);
+    // main walk
+#pragma unroll 2
+    for (int R = R0; R < R1; ++R) strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R, 0);
+}
+
+}  // namespace wz

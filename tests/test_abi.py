@@ -1,0 +1,138 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/weno_zoom.h declares, and rejects bad arguments on the host before
+anything is enqueued (no device memory is touched: the pointers below are
+never dereferenced because validation fails first)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2312_00229_amd import _lib
+from paper_2312_00229_amd._lib import WenoBatchPlan, WenoParams, WenoTensor
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "weno_zoom.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(weno_\w+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("weno_zoom2x", "weno_zoom2x_batched", "weno_zoom2x_backward", "weno_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) <= set(_lib._SIGS)
+
+
+def _t(ptr=0x1000, dtype=_lib.WENO_F32, n=1, c=1, h=4, w=5, contiguous=True):
+    return WenoTensor(ptr, dtype, n, c, h, w, c * h * w, h * w, w, 1)
+
+
+def _p(beta=2.0, keps=1e-8, h=1.0, nbw=-1.0):
+    return WenoParams(beta, keps, h, nbw)
+
+
+def call_zoom(src, dst, p):
+    return _lib.lib().weno_zoom2x(ctypes.byref(src) if src else None, ctypes.byref(dst) if dst else None,
+                                  ctypes.byref(p) if p else None, None)
+
+
+def test_null_and_size_errors():
+    src, dst, p = _t(), _t(ptr=0x100000, h=8, w=10), _p()
+    assert call_zoom(None, dst, p) == _lib.WENO_EINVAL
+    assert call_zoom(src, None, p) == _lib.WENO_EINVAL
+    assert call_zoom(src, dst, None) == _lib.WENO_EINVAL
+    assert call_zoom(_t(ptr=0), dst, p) == _lib.WENO_EINVAL
+    assert call_zoom(_t(h=0), dst, p) == _lib.WENO_EINVAL
+    assert call_zoom(src, _t(ptr=0x100000, h=8, w=9), p) == _lib.WENO_EINVAL   # not 2x
+    assert call_zoom(src, _t(ptr=0x100000, c=2, h=8, w=10), p) == _lib.WENO_EINVAL
+
+
+def test_dtype_error():
+    assert call_zoom(_t(dtype=7), _t(ptr=0x100000, h=8, w=10), _p()) == _lib.WENO_EDTYPE
+
+
+def test_overlap_error():
+    src = _t(ptr=0x100000, h=4, w=5)
+    dst = _t(ptr=0x100000 + 40, h=8, w=10)
+    assert call_zoom(src, dst, _p()) == _lib.WENO_EOVERLAP
+
+
+@pytest.mark.parametrize("p", [_p(beta=-1.0), _p(h=0.0), _p(keps=-1.0), _p(beta=float("nan")),
+                               _p(keps=0.0), _p(beta=10.0, keps=1e-30)])
+def test_parameter_errors(p):
+    assert call_zoom(_t(), _t(ptr=0x100000, h=8, w=10), p) == _lib.WENO_EINVAL
+
+
+def test_beta_zero_allows_zero_eps_validation():
+    # beta = 0 gives equal weights, eps never enters; validation alone (a
+    # shape error is planted so nothing is launched)
+    assert call_zoom(_t(), _t(ptr=0x100000, h=8, w=9), _p(beta=0.0, keps=0.0)) == _lib.WENO_EINVAL
+
+
+def test_batched_errors():
+    L = _lib.lib()
+    src = (WenoTensor * 2)(_t(), _t(ptr=0x2000))
+    dst = (WenoTensor * 2)(_t(ptr=0x100000, h=8, w=10), _t(ptr=0x200000, h=8, w=10))
+    plan = WenoBatchPlan()
+    p = _p()
+    ws = L.weno_zoom2x_batched_workspace(2)
+    assert ws >= 256 and ws % 256 == 0
+    assert L.weno_zoom2x_batched_plan(src, dst, 0, ctypes.byref(p), 0x300000, ws, None, ctypes.byref(plan)) == _lib.WENO_EINVAL
+    assert L.weno_zoom2x_batched_plan(src, dst, 2, ctypes.byref(p), 0x300000, ws - 1, None, ctypes.byref(plan)) == _lib.WENO_ENOSPC
+    assert L.weno_zoom2x_batched_plan(src, dst, 2, ctypes.byref(p), 0x300010, ws, None, ctypes.byref(plan)) == _lib.WENO_EINVAL
+    dst_overlap = (WenoTensor * 2)(_t(ptr=0x100000, h=8, w=10), _t(ptr=0x100000 + 64, h=8, w=10))
+    assert L.weno_zoom2x_batched_plan(src, dst_overlap, 2, ctypes.byref(p), 0x300000, ws, None,
+                                      ctypes.byref(plan)) == _lib.WENO_EOVERLAP
+    assert L.weno_zoom2x_batched_run(None, None) == _lib.WENO_EINVAL
+
+
+def test_cascade_errors():
+    L = _lib.lib()
+    src = _t()
+    dst = _t(ptr=0x100000, h=32, w=40)
+    p = _p()
+    need = L.weno_zoom2x_cascade_workspace(ctypes.byref(src), 3)
+    assert need > 0
+    assert L.weno_zoom2x_cascade(ctypes.byref(src), ctypes.byref(dst), 0, ctypes.byref(p), 0x400000, need, None) == _lib.WENO_EINVAL
+    assert L.weno_zoom2x_cascade(ctypes.byref(src), ctypes.byref(dst), 2, ctypes.byref(p), 0x400000, need, None) == _lib.WENO_EINVAL
+    assert L.weno_zoom2x_cascade(ctypes.byref(src), ctypes.byref(dst), 3, ctypes.byref(p), 0x400000, need - 1, None) == _lib.WENO_ENOSPC
+
+
+def test_backward_errors():
+    L = _lib.lib()
+    x = _t()
+    gy = _t(ptr=0x100000, h=8, w=10)
+    gx = _t(ptr=0x200000)
+    p = _p()
+    assert L.weno_zoom2x_backward(None, ctypes.byref(gy), ctypes.byref(gx), ctypes.byref(p), None) == _lib.WENO_EINVAL
+    assert L.weno_zoom2x_backward(ctypes.byref(_t(dtype=_lib.WENO_U8)), ctypes.byref(gy), ctypes.byref(gx),
+                                  ctypes.byref(p), None) == _lib.WENO_EDTYPE
+    assert L.weno_zoom2x_backward(ctypes.byref(x), ctypes.byref(_t(ptr=0x100000, h=8, w=11)), ctypes.byref(gx),
+                                  ctypes.byref(p), None) == _lib.WENO_EINVAL
+
+
+def test_launch_config_validation():
+    L = _lib.lib()
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    L.weno_get_launch_config(ctypes.byref(r), ctypes.byref(c))
+    assert L.weno_set_launch_config(12, 2) == _lib.WENO_EINVAL
+    assert L.weno_set_launch_config(64, 3) == _lib.WENO_EINVAL
+    assert L.weno_set_launch_config(2048, 1) == _lib.WENO_EINVAL
+    assert L.weno_set_launch_config(r.value, c.value) == _lib.WENO_OK
+
+
+def test_status_strings():
+    for s in (0, -1, -2, -3, -4, -5, -99):
+        assert isinstance(_lib.status_string(s), str)
+    assert _lib.lib().weno_version().decode().count(".") == 2

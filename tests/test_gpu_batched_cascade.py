@@ -1,0 +1,75 @@
+"""GPU: one persistent launch over many uneven images (bit-identical to the
+per-image kernel) and the three-level cascade against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import batch_shapes, pixel_art, scene_rgb
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.mark.parametrize("cfg", [(64, 2), (16, 1)])
+def test_batched_bit_identical_to_single(gpu, cfg):
+    gpu.set_launch_config(*cfg)
+    shapes = batch_shapes(24, seed=3, lo=1, hi=300)
+    imgs = [scene_rgb(h, w, seed=100 + i, n_polygons=5) for i, (h, w) in enumerate(shapes)]
+    xs = [torch.tensor(im, device="cuda").permute(2, 0, 1) for im in imgs]
+    ys = gpu.zoom2x_batched(xs)
+    torch.cuda.synchronize()
+    for x, y in zip(xs, ys):
+        ref = gpu.zoom2x(x)
+        assert torch.equal(y, ref)
+
+
+def test_batched_f32_against_oracle(gpu):
+    gpu.set_launch_config(64, 2)
+    shapes = [(1, 1), (3, 200), (130, 4), (64, 64), (129, 257)]
+    rng = np.random.default_rng(1)
+    xs = [torch.tensor(rng.random((2, h, w)).astype(np.float32), device="cuda") for h, w in shapes]
+    plan = gpu.BatchedZoom(xs, [torch.empty((2, 2 * h, 2 * w), device="cuda") for h, w in shapes])
+    for _ in range(3):  # the plan can be run again; the queue head is reset by a kernel
+        ys = plan.run()
+    torch.cuda.synchronize()
+    for x, y in zip(xs, ys):
+        ref = oracle.zoom2x(x.cpu().numpy().astype(np.float64))
+        assert np.abs(y.cpu().numpy() - ref).max() <= TOL
+
+
+def test_cascade_three_levels(gpu):
+    gpu.set_launch_config(64, 2)
+    img = pixel_art(32, 32, seed=1, block=8, n_lines=4)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    yf = gpu.zoom2x_cascade(x, 3, out_dtype=torch.float32).permute(1, 2, 0).cpu().numpy()
+    ref = oracle.cascade(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 3)
+    assert np.abs(np.transpose(yf, (2, 0, 1)) - ref).max() <= 3 * TOL
+    y8 = gpu.zoom2x_cascade(x, 3).permute(1, 2, 0).cpu().numpy()
+    from conftest import u8_compare
+
+    ties, errors = u8_compare(np.transpose(y8, (2, 0, 1)), ref, tie_band=3 * TOL)
+    assert errors == 0
+
+
+def test_cascade_graph_replay(gpu):
+    gpu.set_launch_config(64, 2)
+    img = pixel_art(48, 40, seed=2, block=8, n_lines=5)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    eager = gpu.zoom2x_cascade(x, 3)
+    ws = torch.empty(gpu.cascade_workspace_bytes(x, 3), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gpu.zoom2x_cascade(x, 3, workspace=ws)  # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        res = gpu.zoom2x_cascade(x, 3, workspace=ws)
+    for _ in range(4):
+        res.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(res, eager)

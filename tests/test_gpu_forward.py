@@ -1,0 +1,169 @@
+"""GPU parity of the forward kernel (weno_zoom2x through the C ABI) against
+the FP64 oracle.
+
+Bar: FP32 outputs within 1e-5 max-abs of the oracle on [0,1]-scaled data;
+originals bit-exact; uint8 codes equal except counted rounding ties."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from conftest import u8_compare
+from workloads import pixel_art, random_plane, scene_rgb, smooth_grid, to_planar_f32
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+CONFIGS = [(64, 2), (64, 1), (8, 2), (16, 1), (128, 2)]
+
+
+def _set(gpu, cfg):
+    gpu.set_launch_config(*cfg)
+
+
+def _f32(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (5, 130), (130, 5), (64, 64), (67, 250), (200, 131), (9, 119), (9, 120),
+          (31, 237)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_forward_matches_oracle_f32(gpu, shape, cfg):
+    _set(gpu, cfg)
+    V = random_plane(*shape, seed=shape[0] * 1000 + shape[1], kind="steps") * 0.7 + 0.3 * random_plane(
+        *shape, seed=7, kind="uniform")
+    V32 = V.astype(np.float32)
+    U = gpu.zoom2x(_f32(V32)).cpu().numpy()
+    ref = oracle.zoom2x(V32.astype(np.float64))
+    assert U.shape == ref.shape
+    assert np.abs(U - ref).max() <= TOL
+    assert np.array_equal(U[0::2, 0::2], V32)  # originals bit-exact
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 2.0, 0.5, 3.0])
+@pytest.mark.parametrize("kind", ["uniform", "binary", "steps"])
+def test_forward_beta(gpu, beta, kind):
+    _set(gpu, (64, 2))
+    V = random_plane(53, 141, seed=int(beta * 10) + 3, kind=kind).astype(np.float32)
+    U = gpu.zoom2x(_f32(V), beta=beta).cpu().numpy()
+    ref = oracle.zoom2x(V.astype(np.float64), beta=beta)
+    assert np.abs(U - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("nbw,h,keps", [(0.125, 1.0, 1e-8), (0.0, 1.0, 1e-8), (-1.0, 0.5, 1e-6), (-1.0, 2.0, 1e-8)])
+def test_forward_parameters(gpu, nbw, h, keps):
+    _set(gpu, (64, 2))
+    V = random_plane(40, 70, seed=11, kind="steps").astype(np.float32)
+    U = gpu.zoom2x(_f32(V), beta=2.0, k_eps=keps, h=h, nbw=nbw).cpu().numpy()
+    ref = oracle.zoom2x(V.astype(np.float64), beta=2.0, keps=keps, h=h, nbw=None if nbw < 0 else nbw)
+    assert np.abs(U - ref).max() <= TOL
+
+
+def test_smooth_function_64(gpu):
+    # the smooth accuracy case: 64 x 64 samples of the test function, 2x
+    _set(gpu, (64, 2))
+    V = smooth_grid(64).astype(np.float32)
+    h = 1.0 / 63
+    U = gpu.zoom2x(_f32(V), h=h).cpu().numpy()
+    ref = oracle.zoom2x(V.astype(np.float64), h=h)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(U - ref).max() <= TOL * scale
+
+
+@pytest.mark.parametrize("cfg", [(64, 2), (16, 1)])
+def test_u8_hwc_scene(gpu, cfg, request):
+    _set(gpu, cfg)
+    img = scene_rgb(97, 263, seed=5, n_polygons=12)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)      # HWC memory, (C, H, W) view
+    y = gpu.zoom2x(x)                                            # uint8, HWC-strided
+    assert y.stride()[0] == 1
+    codes = y.permute(1, 2, 0).cpu().numpy()                     # (2H, 2W, C)
+    ref = oracle.zoom2x(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0)
+    ties, errors = u8_compare(np.transpose(codes, (2, 0, 1)), ref)
+    print("u8 scene: ties %d of %d" % (ties, ref.size))
+    assert errors == 0
+    assert ties <= 1e-3 * ref.size
+    assert np.array_equal(codes[0::2, 0::2], img)
+
+
+def test_u8_to_f32_and_f32_to_u8(gpu):
+    _set(gpu, (64, 2))
+    img = pixel_art(40, 56, seed=4, block=4, n_lines=6)
+    x8 = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    ref = oracle.zoom2x(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0)
+    yf = gpu.zoom2x(x8, out_dtype=torch.float32).permute(1, 2, 0).cpu().numpy()
+    assert np.abs(np.transpose(yf, (2, 0, 1)) - ref).max() <= TOL
+    xf = _f32(np.transpose(img, (2, 0, 1)) / 255.0)
+    y8 = gpu.zoom2x(xf, out_dtype=torch.uint8).cpu().numpy()
+    ties, errors = u8_compare(y8, ref)
+    assert errors == 0
+
+
+def test_strided_views(gpu):
+    _set(gpu, (64, 2))
+    base = random_plane(90, 300, seed=12, kind="steps").astype(np.float32)
+    t = _f32(base)
+    view = t[3:80:2, 5:290:3]          # non-contiguous rows and columns
+    U = gpu.zoom2x(view).cpu().numpy()
+    ref = oracle.zoom2x(view.cpu().numpy().astype(np.float64))
+    assert np.abs(U - ref).max() <= TOL
+    # non-contiguous output
+    out_big = torch.zeros((2 * view.shape[0], 4 * view.shape[1]), device="cuda")
+    out = out_big[:, ::2]
+    gpu.zoom2x_(view, out)
+    assert np.abs(out.cpu().numpy() - ref).max() <= TOL
+    assert float(out_big[:, 1::2].abs().max()) == 0.0
+
+
+def test_batch_of_planes_nchw(gpu):
+    _set(gpu, (32, 2))
+    V = np.stack([random_plane(33, 47, seed=s, kind="steps") for s in range(6)]).reshape(2, 3, 33, 47).astype(np.float32)
+    U = gpu.zoom2x(_f32(V)).cpu().numpy()
+    ref = oracle.zoom2x(V.astype(np.float64))
+    assert np.abs(U - ref).max() <= TOL
+
+
+def test_constant_plane(gpu):
+    _set(gpu, (64, 2))
+    for c in (0.0, 0.25, 1.0):
+        U = gpu.zoom2x(torch.full((37, 91), c, device="cuda")).cpu().numpy()
+        assert np.abs(U - c).max() <= 1e-6 * max(c, 1.0)
+
+
+def test_launch_configs_bit_identical(gpu):
+    img = scene_rgb(150, 333, seed=9, n_polygons=10)
+    x = _f32(np.transpose(img, (2, 0, 1)) / 255.0)
+    outs = []
+    for cfg in [(8, 1), (64, 1), (8, 2), (64, 2), (256, 2)]:
+        _set(gpu, cfg)
+        outs.append(gpu.zoom2x(x).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_full_size_1080p_sampled(gpu):
+    # 1920 x 1080 RGB uint8 scene, zoomed to 3840 x 2160 in the benchmark's
+    # launch configuration; sampled windows (including all four corners and
+    # edges) checked against the oracle computed on windows of the input.
+    _set(gpu, (64, 2))
+    img = scene_rgb(1080, 1920, seed=0)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    y8 = gpu.zoom2x(x).permute(1, 2, 0).cpu().numpy()
+    xf = _f32(to_planar_f32(img))
+    yf = gpu.zoom2x(xf).cpu().numpy()
+    planes = np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0
+    rng = np.random.default_rng(0)
+    windows = [(0, 0), (0, 1920 - 24), (1080 - 24, 0), (1080 - 24, 1920 - 24)]
+    windows += [(int(rng.integers(0, 1080 - 24)), int(rng.integers(0, 1920 - 24))) for _ in range(6)]
+    total_ties = 0
+    for (r0, c0) in windows:
+        ref = oracle.window_zoom2x(planes, r0, r0 + 24, c0, c0 + 24)
+        got_f = yf[:, 2 * r0: 2 * r0 + 48, 2 * c0: 2 * c0 + 48]
+        assert np.abs(got_f - ref).max() <= TOL, (r0, c0)
+        got8 = np.transpose(y8[2 * r0: 2 * r0 + 48, 2 * c0: 2 * c0 + 48], (2, 0, 1))
+        ties, errors = u8_compare(got8, ref)
+        assert errors == 0, (r0, c0)
+        total_ties += ties
+    assert np.array_equal(y8[0::2, 0::2], img)
