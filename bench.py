@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark of the WD-WENO 2x zoom on one MI355X.
+
+Headline (one JSON line on stdout): output Mpix/s of one 2x doubling of a
+1920x1080 RGB float32 frame (planar, [0,1] scale, the polygon scene) to
+3840x2160, with the HBM-roofline fraction of the kernel and the FP64 CPU
+oracle timed beside it.  A "step" is one weno_zoom2x call on that frame,
+inputs resident in HBM.
+
+Extra fields (same line): the uint8 HWC variant of the frame, 512 uneven
+images in one persistent launch vs a per-image launch loop, three fused
+doublings of a 256x256 pixel-art image replayed from a HIP graph, and
+forward+backward of a 16x3x512x512 float32 batch.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = ["paper_2312_00229_amd/csrc/weno_fwd.h", "paper_2312_00229_amd/csrc/weno_api.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zoom2x_rgb_f32_1080p.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed(fn, steps, warmup, torch):
+    """Average ms per call of fn() over `steps` calls after `warmup`, with HIP
+    events on the current stream bracketing the timed region."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(img_planar):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.zoom2x(img_planar.astype(np.float64))
+    dt = time.perf_counter() - t0
+    H, W = img_planar.shape[-2:]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": round(4 * H * W / dt / 1e6, 3),
+        "unit": "output Mpix/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "the full %dx%d RGB frame, one doubling (3 planes), FP64 C oracle, OpenMP" % (W, H),
+        "seconds": round(dt, 3),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--only-main", action="store_true", help="time only the headline kernel (for profilers)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2312_00229_amd as wz
+    from workloads import batch_shapes, pixel_art, scene_rgb, to_planar_f32
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ---------------- headline: 1080p RGB fp32 -> 2160p ----------------
+    H, W = 1080, 1920
+    img = scene_rgb(H, W, seed=0)
+    planar = to_planar_f32(img)
+    x = torch.tensor(planar, device=dev)
+    y = torch.empty((3, 2 * H, 2 * W), dtype=torch.float32, device=dev)
+    log("headline: zoom2x RGB fp32 %dx%d, steps %d warmup %d" % (W, H, args.steps, args.warmup))
+    ms = timed(lambda: wz.zoom2x_(x, y), args.steps, args.warmup, torch)
+    out_px = 4 * H * W
+    value = out_px / (ms * 1e-3) / 1e6
+    alg_bytes = 3 * H * W * 4 + 3 * 4 * H * W * 4
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    rows, cols = wz.get_launch_config()
+    result = {
+        "metric": "output Mpix/s (2x WENO zoom, RGB fp32)",
+        "value": round(value, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "zoom2x 1920x1080 RGB fp32 planar -> 3840x2160, polygon scene (seed 0)",
+            "launch": {"rows_per_strip": rows, "cols_per_lane": cols},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+    }
+    if args.copy_calib:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d bytes read + written" % (a.numel() * 4))
+    if args.only_main:
+        print(json.dumps(result), flush=True)
+        return
+
+    extras = {}
+    # ---------------- uint8 HWC variant of the same frame ----------------
+    x8 = torch.tensor(img, device=dev).permute(2, 0, 1)
+    y8 = torch.empty((2 * H, 2 * W, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1)
+    ms8 = timed(lambda: wz.zoom2x_(x8, y8), args.steps, args.warmup, torch)
+    extras["u8_hwc_1080p"] = {"ms": round(ms8, 5), "Mpix_per_s": round(out_px / (ms8 * 1e-3) / 1e6, 1),
+                              "GBps_algorithmic": round((3 * H * W + 12 * H * W) / (ms8 * 1e-3) / 1e9, 1)}
+    log("u8 HWC 1080p: %.4f ms" % ms8)
+
+    # ---------------- batched: 512 uneven images ----------------
+    shapes = batch_shapes(512, seed=2)
+    rng = np.random.default_rng(2)
+    bases = [scene_rgb(1024, 1024, seed=2000 + k, n_polygons=40) for k in range(8)]
+    imgs = []
+    for i, (h, w) in enumerate(shapes):
+        b = bases[i % len(bases)]
+        r0 = int(rng.integers(0, 1024 - h + 1))
+        c0 = int(rng.integers(0, 1024 - w + 1))
+        imgs.append(b[r0:r0 + h, c0:c0 + w])
+    xs = [torch.tensor(np.ascontiguousarray(im), device=dev).permute(2, 0, 1) for im in imgs]
+    ys = [torch.empty((2 * h, 2 * w, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1) for (h, w) in shapes]
+    plan = wz.BatchedZoom(xs, ys)
+    bsteps = max(3, args.steps // 20)
+    ms_b = timed(plan.run, bsteps, 2, torch)
+
+    def loop():
+        for a, b in zip(xs, ys):
+            wz.zoom2x_(a, b)
+
+    ms_l = timed(loop, bsteps, 2, torch)
+    bpx = sum(4 * h * w for h, w in shapes)
+    extras["batched_512_u8"] = {
+        "ms_persistent": round(ms_b, 4), "ms_launch_loop": round(ms_l, 4),
+        "Mpix_per_s_persistent": round(bpx / (ms_b * 1e-3) / 1e6, 1),
+        "Mpix_per_s_launch_loop": round(bpx / (ms_l * 1e-3) / 1e6, 1),
+        "content": "crops of eight 1024x1024 polygon scenes, sizes U{32..1024}^2 (seed 2)",
+    }
+    log("batched: persistent %.3f ms, loop %.3f ms" % (ms_b, ms_l))
+
+    # ---------------- cascade: 256^2 pixel art, 3 doublings, HIP graph ----------------
+    pa = pixel_art(256, 256, seed=1)
+    xp = torch.tensor(pa, device=dev).permute(2, 0, 1)
+    ws = torch.empty(wz.cascade_workspace_bytes(xp, 3), dtype=torch.uint8, device=dev)
+    outc = [None]
+
+    def casc():
+        outc[0] = wz.zoom2x_cascade(xp, 3, workspace=ws)
+
+    casc()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        casc()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        res = wz.zoom2x_cascade(xp, 3, workspace=ws)
+    ms_g = timed(g.replay, args.steps, args.warmup, torch)
+    ms_e = timed(casc, args.steps, args.warmup, torch)
+    extras["cascade_256_x8_u8"] = {"ms_graph": round(ms_g, 5), "ms_eager": round(ms_e, 5),
+                                   "Mpix_per_s_graph": round(2048 * 2048 / (ms_g * 1e-3) / 1e6, 1)}
+    log("cascade: graph %.4f ms eager %.4f ms" % (ms_g, ms_e))
+    del res
+
+    # ---------------- forward + backward, 16 x 3 x 512 x 512 ----------------
+    try:
+        xb = torch.tensor(np.stack([to_planar_f32(scene_rgb(512, 512, seed=100 + i, n_polygons=20))
+                                    for i in range(16)]), device=dev)
+        gy = torch.randn((16, 3, 1024, 1024), device=dev)
+        yb = torch.empty_like(gy)
+
+        def fwd():
+            wz.zoom2x_(xb, yb)
+
+        def fwdbwd():
+            wz.zoom2x_(xb, yb)
+            wz.zoom2x_backward(xb, gy)
+
+        ms_f = timed(fwd, max(5, args.steps // 10), 3, torch)
+        ms_fb = timed(fwdbwd, max(5, args.steps // 10), 3, torch)
+        opx = 16 * 1024 * 1024
+        extras["fwd_bwd_16x3x512"] = {"ms_fwd": round(ms_f, 4), "ms_fwd_bwd": round(ms_fb, 4),
+                                      "Mpix_per_s_fwd": round(opx / (ms_f * 1e-3) / 1e6, 1),
+                                      "Mpix_per_s_fwd_bwd": round(opx / (ms_fb * 1e-3) / 1e6, 1)}
+        log("fwd %.3f ms, fwd+bwd %.3f ms" % (ms_f, ms_fb))
+    except wz.WenoError as e:
+        extras["fwd_bwd_16x3x512"] = {"error": str(e)}
+
+    result["extras"] = extras
+    if not args.no_cpu:
+        log("cpu baseline (FP64 oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(planar)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

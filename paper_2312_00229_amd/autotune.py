@@ -1,0 +1,96 @@
+"""Launch-configuration autotuner for the forward kernels.
+
+The knobs are the strip height (input rows one wave walks, `rows_per_strip`)
+and the columns of quads each lane owns (`cols_per_lane`, 1 or 2).  Taller
+strips amortise the 9-row pipeline fill, shorter ones give more waves to fill
+the 256 CUs; two columns per lane halve the halo overhead per wave but double
+its registers.  Every configuration computes every quad with the same
+arithmetic, so outputs are bit-identical across configurations; the tuner
+checks that too (a cheap guard against a broken configuration).
+
+Results are cached in a JSON file (env WENO_TUNE_CACHE, default
+~/.cache/weno_zoom_tune.json) keyed by device name, dtypes, channel count and
+a size class of the image.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import get_launch_config, set_launch_config, zoom2x_
+
+ROWS = (16, 24, 32, 48, 64, 96, 128)
+COLS = (1, 2)
+
+
+def _cache_path() -> str:
+    return os.environ.get("WENO_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "weno_zoom_tune.json"))
+
+
+def _key(x: torch.Tensor, out: torch.Tensor) -> str:
+    h, w = x.shape[-2:]
+    planes = int(x.numel() // (h * w))
+    cls = "%dx%d" % (2 ** max(0, round(math.log2(max(h, 1)))), 2 ** max(0, round(math.log2(max(w, 1)))))
+    return "%s|%s->%s|p%d|%s" % (torch.cuda.get_device_name(x.device), x.dtype, out.dtype, planes, cls)
+
+
+def _time(fn, reps: int) -> float:
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(x: torch.Tensor, out: torch.Tensor, reps: int = 30, use_cache: bool = True, verbose: bool = False):
+    """Pick and apply the fastest (rows_per_strip, cols_per_lane) for zooming x
+    into out.  Returns (rows, cols, {config: ms})."""
+    key = _key(x, out)
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        rows, cols = cache[key]["best"]
+        set_launch_config(rows, cols)
+        return rows, cols, cache[key].get("times", {})
+    prev = get_launch_config()
+    times = {}
+    ref = None
+    for cols in COLS:
+        for rows in ROWS:
+            set_launch_config(rows, cols)
+            zoom2x_(x, out)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = out.clone()
+            elif not torch.equal(out, ref):
+                set_launch_config(*prev)
+                raise RuntimeError("launch configuration (%d, %d) changed the result" % (rows, cols))
+            times["%d,%d" % (rows, cols)] = _time(lambda: zoom2x_(x, out), reps)
+            if verbose:
+                print("rows %4d cols %d: %.4f ms" % (rows, cols, times["%d,%d" % (rows, cols)]), flush=True)
+    best = min(times, key=times.get)
+    rows, cols = (int(t) for t in best.split(","))
+    set_launch_config(rows, cols)
+    if use_cache:
+        cache[key] = {"best": [rows, cols], "times": times}
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, path)
+    return rows, cols, times

@@ -1,0 +1,388 @@
+// Adjoint of the WD-WENO 2x doubling for gfx950: dL/dV from dL/dU.
+//
+// Reverse-mode differentiation of arXiv 2312.00229, Section 3 (phase 1:
+// eqs. p, 2Dsmoothness, 2DsmoothnessFinal, alpha, IzrazOmega2d,
+// 2dKombinacija; phase 2: eqs. tezine, IzrazOmega2dRavno,
+// 2dKombinacijaRavno).  At a point with candidates p_k, t_k = eps + D_k and
+// blend u:
+//     du/dp_k = omega_k,   du/dt_k = -beta omega_k (p_k - u) / t_k,
+// t_k takes its own indicator with weight 1 and four neighbour indicators of
+// the same direction with weight w; a candidate and an indicator of a stencil
+// (a, b, c) (nodes -1, 1, 3; g = b - a, dd = a - 2b + c) have
+//     p  = (a + b)/2 - dd/8            dp/d(a,b,c)  = (3/8, 3/4, -1/8)
+//     SI' = (12/13) g^2 + dd^2          dSI'/d(a,b,c) = (-(24/13)g + 2dd, (24/13)g - 4dd, 2dd)
+// (the kernels carry SI' = (12/13) SI; t' = (12/13) t and the formula for
+// du/dt'_k is the same in the scaled variables).
+//
+// Work decomposition: like the forward, one wave walks a strip of 64 input
+// columns (one per lane) down the image; horizontal neighbours come from DPP
+// shifts, so every scatter of the adjoint becomes a gather from adjacent
+// lanes, with no atomics: each dL/dV element is written by exactly one lane,
+// and the result is deterministic.  Iteration s:
+//   forward     the forward pipeline (rows up to s+5), blends of A(s), B(s)
+//               and x(s+2) keep the weight factors the seeds need;
+//   seeds       phase-2 seeds of A(s), B(s) from dL/dU;
+//   p2 adjoint  indicator adjoints of A(s-1) and B(s); stencil adjoints into
+//               dL/dx (rows s-2..s+1) and dL/dV (rows s-2..s+1);
+//   p1 seeds    dL/dx of row s-2 is complete: seeds of x(s-2);
+//   p1 adjoint  indicator adjoints of x(s-3); stencil adjoints into dL/dV
+//               rows s-4..s-1 (input rows reloaded from memory);
+//   output      dL/dV row s-4 is complete: fold clamped rows/columns onto the
+//               edge pixels and store.
+// Valid lanes shrink with every neighbour access: the dL/dV of lanes 9..54 is
+// exact, so a strip owns 38 columns at lanes 13..50 and the four padded
+// columns on either side of the image fall in lanes 9..12 / 51..54.
+#pragma once
+
+#include <stdint.h>
+
+#include "weno_fwd.h"
+
+namespace wz {
+
+constexpr int kBwdOwn = 38;     // columns stored per strip
+constexpr int kBwdLane0 = 13;   // lane of the strip's first owned column
+constexpr int kBwdWarm = 17;    // iterations before the first stored row
+
+struct BwdCtx {
+    const uint8_t* x_plane;    // forward input, float32
+    const uint8_t* gy_plane;   // dL/dU, float32, 2H x 2W
+    uint8_t* gx_plane;         // dL/dV, float32, H x W
+    int64_t x_h, gy_h, gx_h;   // row strides in bytes
+    int32_t x_w, gy_w, gx_w;   // column strides in bytes
+    int32_t H, W;
+};
+
+__device__ __forceinline__ float nbL(float x) { return from_left(x); }   // value of column J-1
+__device__ __forceinline__ float nbR(float x) { return from_right(x); }  // value of column J+1
+
+// blend with the factors of the seeds: om_k = omega_k, dk_k = omega_k (p_k - u) / t_k
+template <int BETA>
+__device__ __forceinline__ float blend_seed(const float (&t)[4], const float (&p)[4], float beta, float (&om)[4],
+                                            float (&dk)[4])
+{
+    float a[4], r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (BETA == 2) {
+            r[k] = rcp(t[k]);
+            a[k] = r[k] * r[k];
+        } else if constexpr (BETA == 1) {
+            r[k] = rcp(t[k]);
+            a[k] = r[k];
+        } else {
+            a[k] = __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(t[k]));
+            r[k] = rcp(t[k]);
+        }
+    }
+    const float S = (a[0] + a[1]) + (a[2] + a[3]);
+    const float N = __builtin_fmaf(a[3], p[3], __builtin_fmaf(a[2], p[2], __builtin_fmaf(a[1], p[1], a[0] * p[0])));
+    const float rS = rcp(S);
+    const float u = N * rS;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) om[k] = a[k] * rS;
+    // p_k - u = sum_j omega_j (p_k - p_j): where one direction dominates
+    // (omega_k ~ 1, t_k ~ eps) the exact p_k - u is far below the rounding of
+    // u itself, while each omega_j (p_k - p_j) keeps its relative precision.
+    const float d01 = p[0] - p[1], d02 = p[0] - p[2], d03 = p[0] - p[3];
+    const float d12 = p[1] - p[2], d13 = p[1] - p[3], d23 = p[2] - p[3];
+    const float e0 = __builtin_fmaf(om[3], d03, __builtin_fmaf(om[2], d02, om[1] * d01));
+    const float e1 = __builtin_fmaf(om[3], d13, __builtin_fmaf(om[2], d12, -(om[0] * d01)));
+    const float e2 = __builtin_fmaf(om[3], d23, -__builtin_fmaf(om[1], d12, om[0] * d02));
+    const float e3 = -__builtin_fmaf(om[2], d23, __builtin_fmaf(om[1], d13, om[0] * d03));
+    dk[0] = (om[0] * e0) * r[0];
+    dk[1] = (om[1] * e1) * r[1];
+    dk[2] = (om[2] * e2) * r[2];
+    dk[3] = (om[3] * e3) * r[3];
+    return u;
+}
+
+// adjoint of one stencil: (ga, gb, gc) from the candidate seed gp, the
+// indicator seed gs, and the stencil's g = b - a and dd = a - 2b + c
+__device__ __forceinline__ void stencil_adj(float gp, float gs, float g, float dd, float& ga, float& gb, float& gc)
+{
+    const float e = gs * dd;                         // half of dSI'/dc times gs
+    const float f = gs * (g * (24.0f / 13.0f));
+    ga = __builtin_fmaf(gp, 0.375f, __builtin_fmaf(e, 2.0f, -f));
+    gb = __builtin_fmaf(gp, 0.75f, __builtin_fmaf(e, -4.0f, f));
+    gc = __builtin_fmaf(gp, -0.125f, 2.0f * e);
+}
+
+__device__ __forceinline__ float load_f(const uint8_t* plane, int64_t rstride, int r, uint32_t coff)
+{
+    return *(const float*)(plane + (int64_t)r * rstride + coff);
+}
+
+template <int BETA>
+__device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c0 = strip_x * kBwdOwn;
+    const int J = c0 - kBwdLane0 + lane;
+    const int H = cx.H, W = cx.W;
+    const bool own = lane >= kBwdLane0 && lane < kBwdLane0 + kBwdOwn && J < W;
+    const bool colin = J >= 0 && J < W;
+    const int jc = J < 0 ? 0 : (J >= W ? W - 1 : J);
+    const uint32_t xoff = (uint32_t)jc * (uint32_t)cx.x_w;
+    const uint32_t gyoffA = (uint32_t)(2 * jc) * (uint32_t)cx.gy_w;        // column 2J
+    const uint32_t gyoffB = (uint32_t)(2 * jc + 1) * (uint32_t)cx.gy_w;    // column 2J+1
+    const uint32_t gxoff = (uint32_t)jc * (uint32_t)cx.gx_w;
+    const bool first_strip = c0 == 0;
+    const bool last_strip = c0 + kBwdOwn >= W;
+    const bool top = R0 == 0, bottom = R1 == H;
+    const float eh = P.eps_hat, w = P.w, beta = P.beta;
+
+    auto ldV = [&](int r) {
+        const int rc = r < 0 ? 0 : (r >= H ? H - 1 : r);
+        return load_f(cx.x_plane, cx.x_h, rc, xoff);
+    };
+    auto ldG = [&](int r, uint32_t off) {   // dL/dU element, 0 outside the 2H x 2W grid
+        float v = 0.0f;
+        if (r >= 0 && r < 2 * H) {
+            const float t = load_f(cx.gy_plane, cx.gy_h, r, off);
+            v = colin ? t : 0.0f;
+        }
+        return v;
+    };
+
+    // ---------------- forward state (rows relative to s) ----------------
+    float V0 = 0, V1 = 0, V2 = 0, V3 = 0, V4 = 0;       // V(s) .. V(s+4)
+    float dd1_3 = 0, dd2s_3 = 0;
+    // indicator windows start at 1 so that pipeline-fill blends never divide by zero
+    float SX1[4] = {1, 1, 1, 1}, SX2[4] = {1, 1, 1, 1}, PX2[4] = {};
+    float X0 = 0, X1 = 0, ddXv0 = 0, ddr0 = 0;
+    float SB0[4] = {1, 1, 1, 1}, PB0[4] = {}, hB0[4] = {1, 1, 1, 1}, hAm1[4] = {1, 1, 1, 1};
+    // stencil geometry (g, dd per direction) of B(s) and A(s-1)
+    float geoB_gv = 0, geoB_ddd = 0, geoB_ddu = 0, geoB_gh = 0, geoB_ddr = 0, geoB_ddl = 0;
+    float geoA_gv = 0, geoA_ddd = 0, geoA_ddu = 0, geoA_gh = 0, geoA_ddr = 0, geoA_ddl = 0;
+    // phase-1 seed factors of x rows s-2 .. s+1
+    float omX[4][4] = {}, dkX[4][4] = {};
+    // ---------------- adjoint state ----------------
+    float gtA_m1[4] = {}, gpA_m1[4] = {}, qA_m1[4] = {}, qB_m1[4] = {};
+    float accX_m2 = 0, accX_m1 = 0, accX_0 = 0;          // dL/dx rows s-2, s-1, s
+    float gtX_m4[4] = {}, gtX_m3[4] = {}, gpX_m3[4] = {};
+    float accV_m4 = 0, accV_m3 = 0, accV_m2 = 0, accV_m1 = 0, accV_0 = 0;  // dL/dV rows s-4 .. s
+    float fold_top = 0, held = 0;
+
+    const int s_end = bottom ? H + 7 : R1 + 3;
+    for (int s = R0 - kBwdWarm; s <= s_end; ++s) {
+        // ======================= forward =======================
+        const float V5 = ldV(s + 5);
+        const float dd1_4 = d2(nbL(V3), V4, nbR(V5));
+        const float dd2_4 = d2(nbR(V3), V4, nbL(V5));
+        const float dd1s_4 = nbR(dd1_4), dd2s_4 = nbR(dd2_4);
+        // x row s+3
+        float SX3[4], PX3[4];
+        {
+            const float a1 = V3, b1 = nbR(V4), a2 = nbR(V3), b2 = V4;
+            const float gc1 = gterm(b1 - a1, eh), gc2 = gterm(b2 - a2, eh);
+            const float m1 = 0.5f * (a1 + b1), m2 = 0.5f * (a2 + b2);
+            SX3[0] = sidx(dd1s_4, gc1);  PX3[0] = cand(dd1s_4, m1);
+            SX3[2] = sidx(dd1_3, gc1);   PX3[2] = cand(dd1_3, m1);
+            SX3[1] = sidx(dd2s_3, gc2);  PX3[1] = cand(dd2s_3, m2);
+            SX3[3] = sidx(dd2_4, gc2);   PX3[3] = cand(dd2_4, m2);
+        }
+        // x row s+2 with its seed factors
+        float X2, omX2[4], dkX2[4];
+        {
+            float t[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float ns = (SX1[k] + SX3[k]) + (nbL(SX2[k]) + nbR(SX2[k]));
+                t[k] = __builtin_fmaf(w, ns, SX2[k]);
+            }
+            X2 = blend_seed<BETA>(t, PX2, beta, omX2, dkX2);
+        }
+        const float ddXv1 = d2(X0, X1, X2);
+        const float ddr1 = d2(V0, V1, V2);
+        // + points: B(s+1) and A(s)
+        float SB1[4], PB1[4], hB1[4], SA0[4], PA0[4], hA0[4];
+        float nB_gv, nB_ddd, nB_ddu, nB_gh, nB_ddr, nB_ddl;   // geometry of B(s+1)
+        float nA_gv, nA_ddd, nA_ddu, nA_gh, nA_ddr, nA_ddl;   // geometry of A(s)
+        {
+            const float v1r = nbR(V1);
+            const float ddc = d2(nbL(V1), V1, v1r);
+            const float x0l = nbL(X0);
+            const float ddXh = d2(x0l, X0, nbR(X0));
+            // B(s+1)
+            nB_gv = X1 - X0;  nB_ddd = ddXv1;  nB_ddu = ddXv0;
+            nB_gh = v1r - V1; nB_ddr = nbR(ddc); nB_ddl = ddc;
+            const float gcv = gterm(nB_gv, eh), mv = 0.5f * (X0 + X1);
+            const float gch = gterm(nB_gh, eh), mh = 0.5f * (V1 + v1r);
+            SB1[0] = sidx(nB_ddd, gcv); PB1[0] = cand(nB_ddd, mv);
+            SB1[2] = sidx(nB_ddu, gcv); PB1[2] = cand(nB_ddu, mv);
+            SB1[1] = sidx(nB_ddr, gch); PB1[1] = cand(nB_ddr, mh);
+            SB1[3] = sidx(nB_ddl, gch); PB1[3] = cand(nB_ddl, mh);
+            // A(s)
+            nA_gv = V1 - V0;  nA_ddd = ddr1;  nA_ddu = ddr0;
+            nA_gh = X0 - x0l; nA_ddr = ddXh;  nA_ddl = nbL(ddXh);
+            const float gav = gterm(nA_gv, eh), mav = 0.5f * (V0 + V1);
+            const float gah = gterm(nA_gh, eh), mah = 0.5f * (x0l + X0);
+            SA0[0] = sidx(nA_ddd, gav); PA0[0] = cand(nA_ddd, mav);
+            SA0[2] = sidx(nA_ddu, gav); PA0[2] = cand(nA_ddu, mav);
+            SA0[1] = sidx(nA_ddr, gah); PA0[1] = cand(nA_ddr, mah);
+            SA0[3] = sidx(nA_ddl, gah); PA0[3] = cand(nA_ddl, mah);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                hB1[k] = nbL(SB1[k]) + SB1[k];
+                hA0[k] = SA0[k] + nbR(SA0[k]);
+            }
+        }
+        // blends of A(s), B(s) with seed factors
+        float omA[4], dkA[4], omB[4], dkB[4];
+        {
+            float ta[4], tb[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ta[k] = __builtin_fmaf(w, hB0[k] + hB1[k], SA0[k]);
+                tb[k] = __builtin_fmaf(w, hAm1[k] + hA0[k], SB0[k]);
+            }
+            (void)blend_seed<BETA>(ta, PA0, beta, omA, dkA);
+            (void)blend_seed<BETA>(tb, PB0, beta, omB, dkB);
+        }
+
+        // ======================= phase-2 seeds =======================
+        const float gA = ldG(2 * s + 1, gyoffA);
+        const float gB = ldG(2 * s, gyoffB);
+        float gtA[4], gpA[4], gtB[4], gpB[4], qA[4], qB[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            gpA[k] = gA * omA[k];
+            gtA[k] = -beta * (gA * dkA[k]);
+            gpB[k] = gB * omB[k];
+            gtB[k] = -beta * (gB * dkB[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            qB[k] = gtB[k] + nbL(gtB[k]);   // gt_B(s, J) + gt_B(s, J-1)
+            qA[k] = gtA[k] + nbR(gtA[k]);   // gt_A(s, J) + gt_A(s, J+1)
+        }
+
+        // ======================= phase-2 adjoint =======================
+        float accX_p1 = 0.0f, accV_p1 = 0.0f;
+        {
+            // A(s-1): indicator seeds gS = gt_A(s-1) + w [gt_B box over rows s-1, s, cols J-1, J]
+            float ga[4], gb[4], gc[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float gs = __builtin_fmaf(w, qB_m1[k] + qB[k], gtA_m1[k]);
+                const float g = (k == 0) ? geoA_gv : (k == 2) ? -geoA_gv : (k == 1) ? geoA_gh : -geoA_gh;
+                const float dd = (k == 0) ? geoA_ddd : (k == 2) ? geoA_ddu : (k == 1) ? geoA_ddr : geoA_ddl;
+                stencil_adj(gpA_m1[k], gs, g, dd, ga[k], gb[k], gc[k]);
+            }
+            // vertical stencils on V column J: k0 (V(s-1), V(s), V(s+1)), k2 (V(s), V(s-1), V(s-2))
+            accV_m1 += ga[0] + gb[2];
+            accV_0 += gb[0] + ga[2];
+            accV_p1 += gc[0];
+            accV_m2 += gc[2];
+            // horizontal stencils on x row s-1: k1 (x[J-1], x[J], x[J+1]), k3 (x[J], x[J-1], x[J-2])
+            const float u = ga[1] + gb[3] + nbR(gc[3]);
+            accX_m1 += (gb[1] + ga[3]) + (nbR(u) + nbL(gc[1]));
+        }
+        {
+            // B(s): gS = gt_B(s) + w [gt_A box over rows s-1, s, cols J, J+1]
+            float ga[4], gb[4], gc[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float gs = __builtin_fmaf(w, qA_m1[k] + qA[k], gtB[k]);
+                const float g = (k == 0) ? geoB_gv : (k == 2) ? -geoB_gv : (k == 1) ? geoB_gh : -geoB_gh;
+                const float dd = (k == 0) ? geoB_ddd : (k == 2) ? geoB_ddu : (k == 1) ? geoB_ddr : geoB_ddl;
+                stencil_adj(gpB[k], gs, g, dd, ga[k], gb[k], gc[k]);
+            }
+            // vertical stencils on x column J: k0 (x(s-1), x(s), x(s+1)), k2 (x(s), x(s-1), x(s-2))
+            accX_m1 += ga[0] + gb[2];
+            accX_0 += gb[0] + ga[2];
+            accX_p1 += gc[0];
+            accX_m2 += gc[2];
+            // horizontal stencils on V row s: k1 (V[J], V[J+1], V[J+2]), k3 (V[J+1], V[J], V[J-1])
+            const float v = gb[1] + ga[3] + nbL(gc[1]);
+            accV_0 += (ga[1] + gb[3]) + (nbL(v) + nbR(gc[3]));
+        }
+
+        // ======================= phase-1 seeds at x row s-2 =======================
+        const float gXc = accX_m2 + ldG(2 * (s - 2) + 1, gyoffB);
+        float gtX_m2[4], gpX_m2[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            gpX_m2[k] = gXc * omX[0][k];
+            gtX_m2[k] = -beta * (gXc * dkX[0][k]);
+        }
+
+        // ======================= phase-1 adjoint at x row r = s-3 =======================
+        {
+            const float Pv = ldV(s - 4), Qv = ldV(s - 3), Rv = ldV(s - 2), Tv = ldV(s - 1);
+            const float dd1_r = d2(nbL(Pv), Qv, nbR(Rv));
+            const float dd1s_r1 = nbR(d2(nbL(Qv), Rv, nbR(Tv)));
+            const float dd2s_r = nbR(d2(nbR(Pv), Qv, nbL(Rv)));
+            const float dd2_r1 = d2(nbR(Qv), Rv, nbL(Tv));
+            const float g1 = nbR(Rv) - Qv;         // V(r+1)[J+1] - V(r)[J]
+            const float g2 = Rv - nbR(Qv);         // V(r+1)[J] - V(r)[J+1]
+            float ga[4], gb[4], gc[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float gs = __builtin_fmaf(w, (gtX_m4[k] + gtX_m2[k]) + (nbL(gtX_m3[k]) + nbR(gtX_m3[k])), gtX_m3[k]);
+                const float g = (k == 0) ? g1 : (k == 2) ? -g1 : (k == 1) ? -g2 : g2;
+                const float dd = (k == 0) ? dd1s_r1 : (k == 2) ? dd1_r : (k == 1) ? dd2s_r : dd2_r1;
+                stencil_adj(gpX_m3[k], gs, g, dd, ga[k], gb[k], gc[k]);
+            }
+            // k0 (V(r)[J], V(r+1)[J+1], V(r+2)[J+2])   k2 (V(r+1)[J+1], V(r)[J], V(r-1)[J-1])
+            // k1 (V(r+1)[J], V(r)[J+1], V(r-1)[J+2])   k3 (V(r)[J+1], V(r+1)[J], V(r+2)[J-1])
+            accV_m4 += nbR(gc[2]) + nbL(nbL(gc[1]));
+            accV_m3 += (ga[0] + gb[2]) + nbL(gb[1] + ga[3]);
+            accV_m2 += (ga[1] + gb[3]) + nbL(gb[0] + ga[2]);
+            accV_m1 += nbL(nbL(gc[0])) + nbR(gc[3]);
+        }
+
+        // ======================= dL/dV row s-4 is complete =======================
+        {
+            const int r = s - 4;
+            float val = accV_m4 + ldG(2 * r, gyoffA);
+            // clamped columns: padded columns -4..-1 fold onto column 0, W..W+3 onto W-1
+            if (first_strip) {
+                float p = J < 0 ? val : 0.0f, acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { p = nbL(p); acc += p; }
+                if (J == 0) val += acc;
+            }
+            if (last_strip) {
+                float q = J >= W ? val : 0.0f, acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { q = nbR(q); acc += q; }
+                if (J == W - 1) val += acc;
+            }
+            // clamped rows: rows -4..-1 fold onto row 0, rows H..H+3 onto row H-1
+            if (top && r < 0) {
+                if (r >= -4) fold_top += val;   // padded rows -4..-1; earlier rows are pipeline fill
+            } else if (bottom && r >= H - 1) {
+                held += (r == H - 1 && top && H == 1) ? val + fold_top : val;
+            } else if (r >= R0 && r < R1) {
+                if (top && r == 0) val += fold_top;
+                if (own) *(float*)(cx.gx_plane + (int64_t)r * cx.gx_h + gxoff) = val;
+            }
+        }
+
+        // ======================= slide the windows =======================
+        V0 = V1; V1 = V2; V2 = V3; V3 = V4; V4 = V5;
+        dd1_3 = dd1_4; dd2s_3 = dd2s_4;
+        X0 = X1; X1 = X2; ddXv0 = ddXv1; ddr0 = ddr1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            SX1[k] = SX2[k]; SX2[k] = SX3[k]; PX2[k] = PX3[k];
+            SB0[k] = SB1[k]; PB0[k] = PB1[k]; hB0[k] = hB1[k]; hAm1[k] = hA0[k];
+            omX[0][k] = omX[1][k]; omX[1][k] = omX[2][k]; omX[2][k] = omX[3][k]; omX[3][k] = omX2[k];
+            dkX[0][k] = dkX[1][k]; dkX[1][k] = dkX[2][k]; dkX[2][k] = dkX[3][k]; dkX[3][k] = dkX2[k];
+            gtA_m1[k] = gtA[k]; gpA_m1[k] = gpA[k]; qA_m1[k] = qA[k]; qB_m1[k] = qB[k];
+            gtX_m4[k] = gtX_m3[k]; gtX_m3[k] = gtX_m2[k]; gpX_m3[k] = gpX_m2[k];
+        }
+        geoB_gv = nB_gv; geoB_ddd = nB_ddd; geoB_ddu = nB_ddu; geoB_gh = nB_gh; geoB_ddr = nB_ddr; geoB_ddl = nB_ddl;
+        geoA_gv = nA_gv; geoA_ddd = nA_ddd; geoA_ddu = nA_ddu; geoA_gh = nA_gh; geoA_ddr = nA_ddr; geoA_ddl = nA_ddl;
+        accX_m2 = accX_m1; accX_m1 = accX_0; accX_0 = accX_p1;
+        accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
+    }
+    if (bottom) {
+        const int r = H - 1;
+        if (r >= R0 && own) *(float*)(cx.gx_plane + (int64_t)r * cx.gx_h + gxoff) = held;
+    }
+}
+
+}  // namespace wz

@@ -1,12 +1,89 @@
-// Adjoint of the WD-WENO 2x zoom (weno_zoom2x_backward).
+// Adjoint of the WD-WENO 2x zoom (weno_zoom2x_backward); the kernel body is
+// in weno_bwd.h.
 #include <hip/hip_runtime.h>
 
+#include "weno_bwd.h"
 #include "weno_internal.h"
 #include "weno_zoom.h"
+
+using namespace wz;
+
+namespace {
+
+template <int BETA>
+__global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdCtx base, int C, int64_t x_n, int64_t x_c,
+                                                            int64_t gy_n, int64_t gy_c, int64_t gx_n, int64_t gx_c,
+                                                            int strips_x, int strips_y, int rows, FwdParams P)
+{
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wave >= strips_x * strips_y) return;  // whole wave
+    const int plane = blockIdx.y;
+    const int n = plane / C, c = plane - n * C;
+    const int sy = wave / strips_x, sx = wave - sy * strips_x;
+    BwdCtx cx = base;
+    cx.x_plane += n * x_n + c * x_c;
+    cx.gy_plane += n * gy_n + c * gy_c;
+    cx.gx_plane += n * gx_n + c * gx_c;
+    const int R0 = sy * rows;
+    const int R1 = min(R0 + rows, cx.H);
+    bwd_strip<BETA>(cx, P, sx, R0, R1);
+}
+
+}  // namespace
+
+FwdParams wz_fwd_params(const weno_params_t* p, int in_u8, int out_u8);
 
 extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, const weno_tensor_t* grad_x,
                                     const weno_params_t* p, void* hip_stream)
 {
-    (void)x; (void)grad_y; (void)grad_x; (void)p; (void)hip_stream;
-    return WENO_EDTYPE;
+    int rc = wz_check_tensor(x);
+    if (rc) return rc;
+    rc = wz_check_tensor(grad_y);
+    if (rc) return rc;
+    rc = wz_check_tensor(grad_x);
+    if (rc) return rc;
+    if (x->dtype != WENO_F32 || grad_y->dtype != WENO_F32 || grad_x->dtype != WENO_F32) return WENO_EDTYPE;
+    rc = wz_check_params(p);
+    if (rc) return rc;
+    if (grad_y->n != x->n || grad_y->c != x->c || (int64_t)grad_y->h != 2ll * x->h || (int64_t)grad_y->w != 2ll * x->w)
+        return WENO_EINVAL;
+    if (grad_x->n != x->n || grad_x->c != x->c || grad_x->h != x->h || grad_x->w != x->w) return WENO_EINVAL;
+    if ((int64_t)x->n * x->c > 65535) return WENO_EINVAL;
+    if ((int64_t)x->w * x->sw * 4 >= (1ll << 31) || (int64_t)grad_y->w * grad_y->sw * 4 >= (1ll << 31) ||
+        (int64_t)grad_x->w * grad_x->sw * 4 >= (1ll << 31))
+        return WENO_EINVAL;
+    if (wz_overlap(grad_x, x) || wz_overlap(grad_x, grad_y)) return WENO_EOVERLAP;
+
+    const int rows = 64;
+    BwdCtx cx;
+    cx.x_plane = (const uint8_t*)x->data;
+    cx.gy_plane = (const uint8_t*)grad_y->data;
+    cx.gx_plane = (uint8_t*)grad_x->data;
+    cx.x_h = x->sh * 4;
+    cx.gy_h = grad_y->sh * 4;
+    cx.gx_h = grad_x->sh * 4;
+    cx.x_w = (int32_t)(x->sw * 4);
+    cx.gy_w = (int32_t)(grad_y->sw * 4);
+    cx.gx_w = (int32_t)(grad_x->sw * 4);
+    cx.H = x->h;
+    cx.W = x->w;
+    const FwdParams P = wz_fwd_params(p, 0, 0);
+    const int strips_x = (x->w + kBwdOwn - 1) / kBwdOwn;
+    const int strips_y = (x->h + rows - 1) / rows;
+    dim3 grid((strips_x * strips_y + kWavesPerBlock - 1) / kWavesPerBlock, x->n * x->c);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int bm = wz_beta_mode(p->beta);
+    if (bm == 2)
+        hipLaunchKernelGGL(zoom2x_bwd_kernel<2>, grid, dim3(kBlock), 0, st, cx, x->c, x->sn * 4, x->sc * 4,
+                           grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x, strips_y, rows, P);
+    else if (bm == 1)
+        hipLaunchKernelGGL(zoom2x_bwd_kernel<1>, grid, dim3(kBlock), 0, st, cx, x->c, x->sn * 4, x->sc * 4,
+                           grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x, strips_y, rows, P);
+    else
+        hipLaunchKernelGGL(zoom2x_bwd_kernel<kBetaGeneral>, grid, dim3(kBlock), 0, st, cx, x->c, x->sn * 4,
+                           x->sc * 4, grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x,
+                           strips_y, rows, P);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wz_hip_error(e, "zoom2x_bwd_kernel launch");
+    return WENO_OK;
 }

@@ -128,6 +128,8 @@ struct StripState {
     float ddXv0[COLS], ddr0[COLS];
     // phase-2: B(R) indicators/candidates, B pair sums at row R, A pair sums at row R-1
     float SB0[4][COLS], PB0[4][COLS], hB0[4][COLS], hAm1[4][COLS];
+    // prefetch queue: input rows R+5 and R+6, loaded two iterations before use
+    float Q0[COLS], Q1[COLS];
 };
 
 struct StripCtx {
@@ -170,7 +172,12 @@ __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int
 {
     uint8_t* r0 = cx.dst_plane + (int64_t)(2 * R) * cx.d_h;
     uint8_t* r1 = r0 + cx.d_h;
-    if (!cx.out_u8) {
+    if (!cx.out_u8 && cx.out_scale == 1.0f && COLS == 2 && cx.vec == 2 && own_all) {
+        // same dtype in and out: no rescaling
+        uint32_t off = (uint32_t)(2 * J[0]) * 4u;
+        *(float4*)(r0 + off) = make_float4(o00[0], o01[0], o00[COLS - 1], o01[COLS - 1]);
+        *(float4*)(r1 + off) = make_float4(o10[0], o11[0], o10[COLS - 1], o11[COLS - 1]);
+    } else if (!cx.out_u8) {
         const float s = cx.out_scale;
         if (COLS == 2 && cx.vec == 2 && own_all) {
             uint32_t off = (uint32_t)(2 * J[0]) * 4u;
@@ -225,7 +232,12 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
     const float eh = P.eps_hat, w = P.w;
 
     float V5[COLS];
-    load_row<COLS>(cx, off, R + 5, V5);
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        V5[c] = s.Q0[c];
+        s.Q0[c] = s.Q1[c];
+    }
+    load_row<COLS>(cx, off, R + 7, s.Q1);
 
     // ---- dd: diagonal second differences centred at (R+4, J) ----
     float dd1_4[COLS] = {}, dd2_4[COLS] = {}, dd1s_4[COLS] = {}, dd2s_4[COLS] = {};
@@ -398,16 +410,26 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
         s.dd1_3[c] = s.dd2s_3[c] = s.X0[c] = s.X1[c] = s.ddXv0[c] = s.ddr0[c] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            s.SX1[k][c] = s.SX2[k][c] = s.PX2[k][c] = 0.0f;
-            s.SB0[k][c] = s.PB0[k][c] = s.hB0[k][c] = s.hAm1[k][c] = 0.0f;
+            // indicator windows start at 1 so that pipeline-fill blends never divide by zero
+            s.SX1[k][c] = s.SX2[k][c] = 1.0f;
+            s.PX2[k][c] = 0.0f;
+            s.SB0[k][c] = s.hB0[k][c] = s.hAm1[k][c] = 1.0f;
+            s.PB0[k][c] = 0.0f;
         }
     }
 
+    load_row<COLS>(cx, off, R0 - 4, s.Q0);
+    load_row<COLS>(cx, off, R0 - 3, s.Q1);
     // prologue: rows R0-9 .. R0-1 fill the pipeline (no stores)
     for (int d = -9; d < 0; ++d) strip_step<COLS, BETA, false>(s, cx, P, off, J, own_all, own, R0 + d, d);
-    // main walk
-#pragma unroll 2
-    for (int R = R0; R < R1; ++R) strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R, 0);
+    // main walk, two rows per trip so that values carried one row are renamed
+    // rather than copied
+    int R = R0;
+    for (; R + 1 < R1; R += 2) {
+        strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R, 0);
+        strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R + 1, 0);
+    }
+    if (R < R1) strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R, 0);
 }
 
 }  // namespace wz

@@ -1,0 +1,142 @@
+"""GPU parity of the adjoint kernel (weno_zoom2x_backward through the C ABI)
+against the oracle's hand adjoint (itself pinned to torch FP64 autograd and
+central finite differences in the CPU suite).
+
+Tolerance: FP32 seeds carry (p_k - u)/t_k, a difference of O(1) values
+divided by an O(h^2) quantity in smooth regions, so relative rounding of the
+largest gradient entries reaches ~2e-5; the bar is max-abs error
+<= 1e-4 * max(1, max|ref|)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import random_plane, scene_rgb, to_planar_f32
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-4
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def _ref(V, G, **kw):
+    return oracle.backward(V.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64), **kw)
+
+
+def _close(got, ref):
+    return np.abs(got - ref).max() <= RTOL * max(1.0, np.abs(ref).max())
+
+
+SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (7, 77), (40, 39), (65, 120), (130, 37), (64, 38), (3, 200)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_backward_matches_oracle(gpu, shape):
+    rng = np.random.default_rng(shape[0] * 7 + shape[1])
+    V = random_plane(*shape, seed=5, kind="steps") * 0.7 + 0.3 * rng.random(shape)
+    G = rng.standard_normal((2 * shape[0], 2 * shape[1]))
+    got = gpu.zoom2x_backward(_t(V), _t(G)).cpu().numpy()
+    assert _close(got, _ref(V, G))
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 2.0, 3.0])
+@pytest.mark.parametrize("kind", ["uniform", "binary", "steps"])
+def test_backward_beta(gpu, beta, kind):
+    rng = np.random.default_rng(int(beta * 10) + 1)
+    V = random_plane(33, 71, seed=9, kind=kind)
+    G = rng.standard_normal((66, 142))
+    p = gpu.Params(beta=beta)
+    got = gpu.zoom2x_backward(_t(V), _t(G), p).cpu().numpy()
+    assert _close(got, _ref(V, G, beta=beta))
+
+
+@pytest.mark.parametrize("nbw,h", [(0.125, 1.0), (0.0, 1.0), (-1.0, 0.25)])
+def test_backward_parameters(gpu, nbw, h):
+    rng = np.random.default_rng(3)
+    V = random_plane(20, 50, seed=2, kind="steps") * 0.5 + 0.5 * rng.random((20, 50))
+    G = rng.standard_normal((40, 100))
+    got = gpu.zoom2x_backward(_t(V), _t(G), gpu.Params(nbw=nbw, h=h)).cpu().numpy()
+    assert _close(got, _ref(V, G, nbw=None if nbw < 0 else nbw, h=h))
+
+
+def test_backward_batch_and_strides(gpu):
+    rng = np.random.default_rng(4)
+    V = rng.random((2, 3, 21, 45)).astype(np.float32)
+    G = rng.standard_normal((2, 3, 42, 90)).astype(np.float32)
+    got = gpu.zoom2x_backward(_t(V), _t(G)).cpu().numpy()
+    assert _close(got, _ref(V, G))
+    # channels-interleaved input view
+    x_hwc = _t(np.transpose(V[0], (1, 2, 0))).permute(2, 0, 1)
+    got2 = gpu.zoom2x_backward(x_hwc, _t(G[0])).cpu().numpy()
+    assert _close(got2, _ref(V[0], G[0]))
+
+
+def test_backward_deterministic(gpu):
+    rng = np.random.default_rng(5)
+    x = _t(rng.random((3, 100, 150)))
+    g = _t(rng.standard_normal((3, 200, 300)))
+    a = gpu.zoom2x_backward(x, g)
+    b = gpu.zoom2x_backward(x, g)
+    assert torch.equal(a, b)
+
+
+def test_autograd_function(gpu):
+    rng = np.random.default_rng(6)
+    V = rng.random((3, 24, 31))
+    x = _t(V).requires_grad_(True)
+    y = gpu.WenoZoom2x.apply(x)
+    G = rng.standard_normal(y.shape)
+    (y * _t(G)).sum().backward()
+    assert _close(x.grad.cpu().numpy(), _ref(V, G))
+
+
+def test_finite_differences_fp64_16x16(gpu):
+    # directional derivative of the FP64 oracle forward along a random
+    # direction equals <grad, direction> of the GPU gradient
+    rng = np.random.default_rng(7)
+    V = rng.random((16, 16))
+    G = rng.standard_normal((32, 32))
+    D = rng.standard_normal((16, 16))
+    eps = 1e-6
+    fd = ((oracle.zoom2x(V + eps * D) - oracle.zoom2x(V - eps * D)) * G).sum() / (2 * eps)
+    got = gpu.zoom2x_backward(_t(V), _t(G)).cpu().numpy().astype(np.float64)
+    assert abs((got * D).sum() - fd) <= 1e-4 * max(1.0, abs(fd))
+
+
+def test_full_size_sampled_windows(gpu):
+    # 16 x 3 x 512 x 512 float32 batch; gradient windows checked against the
+    # oracle adjoint computed on input windows 12 pixels larger on each side
+    imgs = np.stack([to_planar_f32(scene_rgb(512, 512, seed=100 + i, n_polygons=20)) for i in range(16)])
+    rng = np.random.default_rng(8)
+    G = rng.standard_normal((16, 3, 1024, 1024)).astype(np.float32)
+    got = gpu.zoom2x_backward(_t(imgs), _t(G)).cpu().numpy()
+    M = 12
+    for (b, c, r0, c0) in [(0, 0, 0, 0), (3, 1, 500, 490), (15, 2, 200, 300), (7, 0, 0, 480), (9, 2, 490, 0)]:
+        r1, c1 = r0 + 12, c0 + 12
+        wr0, wr1 = max(0, r0 - M), min(512, r1 + M)
+        wc0, wc1 = max(0, c0 - M), min(512, c1 + M)
+        Vw = imgs[b, c, wr0:wr1, wc0:wc1]
+        Gw = G[b, c, 2 * wr0:2 * wr1, 2 * wc0:2 * wc1]
+        ref = _ref(Vw, Gw)[r0 - wr0:r1 - wr0, c0 - wc0:c1 - wc0]
+        assert _close(got[b, c, r0:r1, c0:c1], ref), (b, c, r0, c0)
+
+
+def test_inverse_problem_recovers_input(gpu):
+    # recoverable inverse problem: target = zoom2x(x*); fit x from 0.5 with Adam
+    torch.manual_seed(0)
+    xs = torch.rand((3, 32, 32), device="cuda")
+    target = gpu.zoom2x(xs)
+    x = torch.full_like(xs, 0.5).requires_grad_(True)
+    opt = torch.optim.Adam([x], lr=1e-2)
+    first = None
+    for it in range(300):
+        opt.zero_grad()
+        loss = torch.mean((gpu.WenoZoom2x.apply(x) - target) ** 2)
+        loss.backward()
+        opt.step()
+        if first is None:
+            first = float(loss)
+    assert float(loss) < 1e-3 * first
+    assert float((x - xs).abs().max()) < 0.05
