@@ -145,6 +145,36 @@ int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t* dst, int3
                         const weno_params_t* p, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * Tensor-product WENO resampling (Section 3.3, eq. tensor): every plane of
+ * src (n, c, h, w) is resampled to dst (n, c, H, W) of ANY size with the 1D
+ * WENO spline of Section 2 (eqs. Tocnost .. IzrazOmega; ideal weights
+ * C_0 = (2 - t)/3, C_1 = (t + 1)/3 on [x_i, x_{i+1}]) along the rows, then
+ * along the columns.  End points are aligned: output sample j of an axis sits
+ * at input coordinate j (h_in - 1)/(h_out - 1); samples on input nodes are
+ * copied exactly; samples beyond the ends are clamped.  eps = k_eps h^2 as for
+ * the doubling (nbw is unused).
+ *   d_workspace: DEVICE memory of at least weno_resample_workspace(src, dst)
+ *                bytes (an FP32 (n, c, H, w) intermediate).
+ */
+size_t weno_resample_workspace(const weno_tensor_t* src, const weno_tensor_t* dst);
+int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, void* d_workspace,
+                  size_t ws_bytes, void* hip_stream);
+
+/*
+ * Zoom to ANY size (Section 3.3): k WD-WENO doublings, k the least with
+ * 2^k (h - 1) + 1 >= H and 2^k (w - 1) + 1 >= W (an axis of one sample is not
+ * doubled), each level doubling the paper's (2h'-1) x (2w'-1) grid of the
+ * previous level with the spacing halved, then weno_resample of the
+ * (2^k (h-1) + 1) x (2^k (w-1) + 1) grid to (H, W).  k = 0 (a target no larger
+ * than the source) is plain resampling.
+ *   d_workspace: DEVICE memory of at least weno_zoom_to_workspace(src, dst)
+ *                bytes (FP32 intermediates).  Kernels only: capturable.
+ */
+size_t weno_zoom_to_workspace(const weno_tensor_t* src, const weno_tensor_t* dst);
+int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, void* d_workspace,
+                 size_t ws_bytes, void* hip_stream);
+
+/*
  * Adjoint of weno_zoom2x: grad_x = (d out / d x)^T grad_y for the forward
  * input x (clamped reads fold their gradient onto the edge pixels).  The
  * smoothness indicators, weights and blends of both phases are
@@ -160,9 +190,15 @@ int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, co
 
 /*
  * Launch configuration of the forward kernels (process-global, read at each
- * call; chosen by the Python autotuner).
- *   rows_per_strip: output rows one wave walks down, multiple of 8 in [8, 1024]
+ * call; the Python autotuner sets it).
+ *   rows_per_strip: output rows one wave walks down, in [4, 4096]
  *   cols_per_lane:  1 or 2 columns of quads per lane
+ * (0, 0) selects the automatic choice (the default): two columns per lane for
+ * images at least 256 wide, and a strip height (8..64 rows) that gives about
+ * two waves per SIMD of the device.  The configuration changes speed only: every
+ * configuration produces bit-identical outputs.  Batched plans capture the
+ * configuration when they are made (automatic: 32 rows, 2 columns).
+ * weno_get_launch_config reports (0, 0) in automatic mode.
  * Returns WENO_EINVAL for values outside these sets.
  */
 int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane);

@@ -28,6 +28,8 @@ __all__ = [
     "BatchedZoom",
     "zoom2x_cascade",
     "zoom2x_backward",
+    "resample",
+    "zoom_to",
     "WenoZoom2x",
     "set_launch_config",
     "get_launch_config",
@@ -179,6 +181,48 @@ def zoom2x_backward(x: torch.Tensor, grad_y: torch.Tensor, params: Params | None
     _lib.check(_lib.lib().weno_zoom2x_backward(ctypes.byref(a), ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),
                                                _stream(x.device)), "weno_zoom2x_backward")
     return gx
+
+
+def _sized_like_layout(x: torch.Tensor, out_h: int, out_w: int, dtype) -> torch.Tensor:
+    shape = list(x.shape)
+    shape[-2], shape[-1] = int(out_h), int(out_w)
+    if x.dim() >= 3 and x.stride(-3) == 1 and x.shape[-3] > 1:
+        perm_shape = shape[:-3] + [shape[-2], shape[-1], shape[-3]]
+        out = torch.empty(perm_shape, dtype=dtype, device=x.device)
+        nd = out.dim()
+        return out.permute(*range(nd - 3), nd - 1, nd - 3, nd - 2)
+    return torch.empty(shape, dtype=dtype, device=x.device)
+
+
+def _ws_call(fn_ws, fn, what, x, out, params, workspace):
+    p = (params or Params()).c()
+    s, d = _desc(x), _desc(out)
+    need = int(fn_ws(ctypes.byref(s), ctypes.byref(d)))
+    if need == 0:
+        _lib.check(_lib.WENO_EINVAL, what)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _lib.check(fn(ctypes.byref(s), ctypes.byref(d), ctypes.byref(p), workspace.data_ptr(), workspace.numel(),
+                  _stream(x.device)), what)
+    return out
+
+
+def resample(x: torch.Tensor, out_h: int, out_w: int, params: Params | None = None, out_dtype=None,
+             workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Tensor-product WENO resampling of every (H, W) plane to (out_h, out_w)
+    (eq. tensor), end points aligned."""
+    out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
+    L = _lib.lib()
+    return _ws_call(L.weno_resample_workspace, L.weno_resample, "weno_resample", x, out, params, workspace)
+
+
+def zoom_to(x: torch.Tensor, out_h: int, out_w: int, params: Params | None = None, out_dtype=None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Zoom to any size (Section 3.3): WD-WENO doublings to the first nested
+    grid at least as large, then tensor-WENO resampling."""
+    out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
+    L = _lib.lib()
+    return _ws_call(L.weno_zoom_to_workspace, L.weno_zoom_to, "weno_zoom_to", x, out, params, workspace)
 
 
 class WenoZoom2x(torch.autograd.Function):

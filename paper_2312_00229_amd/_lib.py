@@ -70,6 +70,10 @@ _SIGS = {
     "weno_zoom2x_cascade_workspace": (ctypes.c_size_t, [_T, ctypes.c_int32]),
     "weno_zoom2x_cascade": (_I, [_T, _T, ctypes.c_int32, _P, _V, ctypes.c_size_t, _V]),
     "weno_zoom2x_backward": (_I, [_T, _T, _T, _P, _V]),
+    "weno_resample_workspace": (ctypes.c_size_t, [_T, _T]),
+    "weno_resample": (_I, [_T, _T, _P, _V, ctypes.c_size_t, _V]),
+    "weno_zoom_to_workspace": (ctypes.c_size_t, [_T, _T]),
+    "weno_zoom_to": (_I, [_T, _T, _P, _V, ctypes.c_size_t, _V]),
     "weno_set_launch_config": (_I, [ctypes.c_int32, ctypes.c_int32]),
     "weno_get_launch_config": (None, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "weno_status_string": (ctypes.c_char_p, [_I]),

@@ -22,7 +22,7 @@ import torch
 
 from . import get_launch_config, set_launch_config, zoom2x_
 
-ROWS = (16, 24, 32, 48, 64, 96, 128)
+ROWS = (8, 12, 16, 20, 24, 27, 32, 40, 48, 64, 96)
 COLS = (1, 2)
 
 

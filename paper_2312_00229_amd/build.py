@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libweno_zoom.so")
-SOURCES = ["weno_api.hip", "weno_bwd.hip"]
+SOURCES = ["weno_api.hip", "weno_bwd.hip", "weno_resample.hip"]
 ARCH = os.environ.get("WENO_OFFLOAD_ARCH", "gfx950")
 
 

@@ -22,29 +22,38 @@ using namespace wz;
 // --------------------------------------------------------------------------
 namespace {
 
-template <int COLS, int BETA>
-__global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
+// per-plane context: buffer resources over the plane's byte extent
+__device__ __forceinline__ StripCtx make_ctx(const FwdJob& jb, int n, int c, float out_scale)
 {
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int per_plane = jb.strips_x * jb.strips_y;
-    if (wave >= per_plane) return;  // whole wave
-    const int plane = blockIdx.y;
-    const int sy = wave / jb.strips_x;
-    const int sx = wave - sy * jb.strips_x;
     StripCtx cx;
-    const int n = plane / jb.C, c = plane - n * jb.C;
-    cx.src_plane = jb.src + n * jb.s_n + c * jb.s_c;
-    cx.dst_plane = jb.dst + n * jb.d_n + c * jb.d_c;
-    cx.s_h = jb.s_h;
-    cx.s_w_bytes = (int32_t)jb.s_w;
-    cx.d_h = jb.d_h;
-    cx.d_w = jb.d_w;
+    cx.src = make_rsrc(jb.src + n * jb.s_n + c * jb.s_c, jb.src_extent);
+    cx.dst = make_rsrc(jb.dst + n * jb.d_n + c * jb.d_c, jb.dst_extent);
+    cx.s_h = (uint32_t)jb.s_h;
+    cx.s_w_bytes = (uint32_t)jb.s_w;
+    cx.d_h = (uint32_t)jb.d_h;
+    cx.d_w = (uint32_t)jb.d_w;
     cx.H = jb.H;
     cx.W = jb.W;
     cx.in_u8 = jb.in_u8;
     cx.out_u8 = jb.out_u8;
     cx.vec = jb.vec;
-    cx.out_scale = P.out_scale;
+    cx.out_scale = out_scale;
+    return cx;
+}
+
+template <int COLS, int BETA>
+__global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
+{
+    // the wave index is the same in every lane; say so, so that strip rows and
+    // buffer offsets live in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    const int per_plane = jb.strips_x * jb.strips_y;
+    if (wave >= per_plane) return;  // whole wave
+    const int plane = blockIdx.y;
+    const int sy = wave / jb.strips_x;
+    const int sx = wave - sy * jb.strips_x;
+    const int n = plane / jb.C, c = plane - n * jb.C;
+    const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
     const int R0 = sy * rows_per_strip;
     const int R1 = min(R0 + rows_per_strip, jb.H);
     zoom_strip<COLS, BETA>(cx, P, sx, R0, R1);
@@ -53,19 +62,27 @@ __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, 
 // Persistent kernel over a work queue of strips of many images.  Item i of
 // image k covers plane (i / per_plane) and strip (i % per_plane); images are
 // stored in the table largest first, so the queue drains big items early.
+// The table is read-only during the launch and the queue head is reached
+// through its own pointer, so table reads compile to scalar loads.
 template <int COLS, int BETA>
-__global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable* tab, int rows_per_strip)
+__global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable* __restrict__ tab,
+                                                                unsigned long long* __restrict__ counter,
+                                                                int rows_per_strip)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int count = tab->count;
     const int64_t total = tab->total_items;
-    const FwdJob* jobs = batch_jobs(tab);
-    const int64_t* prefix = batch_prefix(tab);
-    unsigned long long* counter = &((BatchTable*)tab)->counter;
+    const FwdJob* __restrict__ jobs = batch_jobs(tab);
+    const int64_t* __restrict__ prefix = batch_prefix(tab);
     for (;;) {
-        unsigned long long item = 0;
-        if (lane == 0) item = atomicAdd(counter, 1ull);
-        item = __shfl(item, 0);
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(counter, 1ull);
+        // broadcast lane 0's ticket as a provably uniform (scalar) value, so the
+        // image table is read with scalar loads and the buffer resources stay
+        // in SGPRs
+        const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)got);
+        const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+        const unsigned long long item = ((unsigned long long)hi32 << 32) | lo32;
         if ((int64_t)item >= total) break;  // every wave reaches this exit
         // image k with prefix[k] <= item < prefix[k+1]
         int lo = 0, hi = count - 1;
@@ -80,21 +97,9 @@ __global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable
         const int wv = (int)(local - (int64_t)plane * per_plane);
         const int sy = wv / jb.strips_x;
         const int sx = wv - sy * jb.strips_x;
-        StripCtx cx;
         const int n = plane / jb.C, c = plane - n * jb.C;
-        cx.src_plane = jb.src + n * jb.s_n + c * jb.s_c;
-        cx.dst_plane = jb.dst + n * jb.d_n + c * jb.d_c;
-        cx.s_h = jb.s_h;
-        cx.s_w_bytes = (int32_t)jb.s_w;
-        cx.d_h = jb.d_h;
-        cx.d_w = jb.d_w;
-        cx.H = jb.H;
-        cx.W = jb.W;
-        cx.in_u8 = jb.in_u8;
-        cx.out_u8 = jb.out_u8;
-        cx.vec = jb.vec;
         const FwdParams P = batch_params(tab)[lo];
-        cx.out_scale = P.out_scale;
+        const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
         const int R0 = sy * rows_per_strip;
         const int R1 = min(R0 + rows_per_strip, jb.H);
         zoom_strip<COLS, BETA>(cx, P, sx, R0, R1);
@@ -112,8 +117,9 @@ __global__ void reset_counter_kernel(BatchTable* tab)
 // status / configuration
 // --------------------------------------------------------------------------
 static thread_local std::string g_status_text;
-static std::atomic<int32_t> g_rows_per_strip{64};
-static std::atomic<int32_t> g_cols_per_lane{2};
+// 0 / 0 = automatic (chosen per launch from the image size)
+static std::atomic<int32_t> g_rows_per_strip{0};
+static std::atomic<int32_t> g_cols_per_lane{0};
 
 int wz_hip_error(hipError_t e, const char* what)
 {
@@ -150,7 +156,12 @@ extern "C" weno_params_t weno_default_params(void)
 
 extern "C" int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane)
 {
-    if (rows_per_strip < 8 || rows_per_strip > 1024 || rows_per_strip % 8 != 0) return WENO_EINVAL;
+    if (rows_per_strip == 0 && cols_per_lane == 0) {  // back to automatic
+        g_rows_per_strip.store(0);
+        g_cols_per_lane.store(0);
+        return WENO_OK;
+    }
+    if (rows_per_strip < 4 || rows_per_strip > 4096) return WENO_EINVAL;
     if (cols_per_lane != 1 && cols_per_lane != 2) return WENO_EINVAL;
     g_rows_per_strip.store(rows_per_strip);
     g_cols_per_lane.store(cols_per_lane);
@@ -184,6 +195,13 @@ void wz_byte_range(const weno_tensor_t* t, uintptr_t* lo, uintptr_t* hi)
                           (int64_t)(t->w - 1) * t->sw) * es;
     *lo = (uintptr_t)t->data;
     *hi = (uintptr_t)t->data + (uintptr_t)last + (uintptr_t)es;
+}
+
+// bytes spanned by one (h, w) plane of t
+int64_t wz_plane_extent(const weno_tensor_t* t)
+{
+    const int64_t es = wz_esize(t->dtype);
+    return ((int64_t)(t->h - 1) * t->sh + (int64_t)(t->w - 1) * t->sw) * es + es;
 }
 
 bool wz_overlap(const weno_tensor_t* a, const weno_tensor_t* b)
@@ -263,7 +281,8 @@ FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols,
         vec = a16 ? 2 : (a8 ? 1 : 0);
     }
     jb.vec = vec;
-    jb.pad_ = 0;
+    jb.src_extent = (uint32_t)wz_plane_extent(src);
+    jb.dst_extent = (uint32_t)wz_plane_extent(dst);
     return jb;
 }
 
@@ -277,9 +296,8 @@ int wz_check_pair(const weno_tensor_t* src, const weno_tensor_t* dst, int factor
     if (dst->n != src->n || dst->c != src->c) return WENO_EINVAL;
     if ((int64_t)dst->h != (int64_t)src->h * factor || (int64_t)dst->w != (int64_t)src->w * factor) return WENO_EINVAL;
     if ((int64_t)src->n * src->c > 65535) return WENO_EINVAL;
-    // per-lane column offsets are 32-bit
-    if ((int64_t)src->w * src->sw * wz_esize(src->dtype) >= (1ll << 31)) return WENO_EINVAL;
-    if ((int64_t)dst->w * dst->sw * wz_esize(dst->dtype) >= (1ll << 31)) return WENO_EINVAL;
+    // buffer offsets are 32-bit: every plane must span less than 2^31 bytes
+    if (wz_plane_extent(src) >= (1ll << 31) || wz_plane_extent(dst) >= (1ll << 31)) return WENO_EINVAL;
     if (wz_overlap(src, dst)) return WENO_EOVERLAP;
     return WENO_OK;
 }
@@ -297,6 +315,48 @@ static hipError_t launch_fwd_cols(const FwdJob& jb, const FwdParams& P, int beta
     else
         hipLaunchKernelGGL((zoom2x_kernel<COLS, kBetaGeneral>), grid, block, 0, st, jb, P, rows);
     return hipGetLastError();
+}
+
+// SIMDs of the current device (4 per compute unit), cached per device
+static int device_simds()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+    int v = cache[dev].load();
+    if (v == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        v = 4 * cus;
+        cache[dev].store(v);
+    }
+    return v;
+}
+
+// Automatic launch configuration: two quad columns per lane for images at
+// least 256 wide; the strip height splits every strip column into bands so
+// that the launch has about two equal waves per SIMD (waves are independent
+// and equally long, so equal counts per SIMD finish together), but never
+// below 8 rows (the 9-row pipeline fill) or above 64.
+void wz_auto_config(int64_t planes, int H, int W, int* rows, int* cols)
+{
+    const int c = W >= 256 ? 2 : 1;
+    const int own = c == 1 ? kWave - 9 : 2 * kWave - 10;
+    const int64_t columns = planes * ((W + own - 1) / own);
+    const int64_t target = 2 * (int64_t)device_simds();
+    int64_t bands = (target + columns / 2) / columns;
+    if (bands < 1) bands = 1;
+    int r = (int)((H + bands - 1) / bands);
+    r = r < 8 ? 8 : (r > 64 ? 64 : r);
+    *rows = r;
+    *cols = c;
+}
+
+void wz_config_for(const weno_tensor_t* src, int* rows, int* cols)
+{
+    *rows = g_rows_per_strip.load();
+    *cols = g_cols_per_lane.load();
+    if (*rows == 0 || *cols == 0) wz_auto_config((int64_t)src->n * src->c, src->h, src->w, rows, cols);
 }
 
 int wz_launch_fwd(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, hipStream_t st,
@@ -320,7 +380,9 @@ extern "C" int weno_zoom2x(const weno_tensor_t* src, const weno_tensor_t* dst, c
     if (rc) return rc;
     rc = wz_check_params(p);
     if (rc) return rc;
-    return wz_launch_fwd(src, dst, p, (hipStream_t)hip_stream, g_rows_per_strip.load(), g_cols_per_lane.load());
+    int rows, cols;
+    wz_config_for(src, &rows, &cols);
+    return wz_launch_fwd(src, dst, p, (hipStream_t)hip_stream, rows, cols);
 }
 
 // --------------------------------------------------------------------------
@@ -363,7 +425,11 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
             if (v.out) end_out = std::max(end_out, v.hi); else end_in = std::max(end_in, v.hi);
         }
     }
-    const int rows = g_rows_per_strip.load(), cols = g_cols_per_lane.load();
+    int rows = g_rows_per_strip.load(), cols = g_cols_per_lane.load();
+    if (rows == 0 || cols == 0) {  // the queue balances the load: moderate strips, two columns per lane
+        rows = 32;
+        cols = 2;
+    }
     // largest images first
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -418,18 +484,19 @@ static hipError_t launch_batched_cols(const weno_batch_plan_t* plan, hipStream_t
     if (blocks > by_work) blocks = by_work;
     if (blocks < 1) blocks = 1;
     const BatchTable* tab = (const BatchTable*)plan->d_workspace;
+    unsigned long long* counter = &((BatchTable*)plan->d_workspace)->counter;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, (BatchTable*)plan->d_workspace);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (plan->beta_mode == 2)
         hipLaunchKernelGGL((zoom2x_batched_kernel<COLS, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tab,
-                           plan->rows_per_strip);
+                           counter, plan->rows_per_strip);
     else if (plan->beta_mode == 1)
         hipLaunchKernelGGL((zoom2x_batched_kernel<COLS, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, st, tab,
-                           plan->rows_per_strip);
+                           counter, plan->rows_per_strip);
     else
         hipLaunchKernelGGL((zoom2x_batched_kernel<COLS, kBetaGeneral>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           tab, plan->rows_per_strip);
+                           tab, counter, plan->rows_per_strip);
     return hipGetLastError();
 }
 
@@ -492,7 +559,6 @@ extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t
         if (!d_workspace) return WENO_EINVAL;
         if (ws_bytes < weno_zoom2x_cascade_workspace(src, levels)) return WENO_ENOSPC;
     }
-    const int rows = g_rows_per_strip.load(), cols = g_cols_per_lane.load();
     weno_tensor_t cur = *src;
     size_t off = 0;
     weno_params_t lp = *p;
@@ -524,6 +590,8 @@ extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t
         const double scale = std::ldexp(1.0, -l);
         lp.h = (float)(p->h * scale);
         lp.nbw = (float)(w0 * scale * scale);
+        int rows, cols;
+        wz_config_for(&cur, &rows, &cols);
         rc = wz_launch_fwd(&cur, &out, &lp, (hipStream_t)hip_stream, rows, cols);
         if (rc) return rc;
         cur = out;

@@ -45,11 +45,9 @@ constexpr int kBwdLane0 = 13;   // lane of the strip's first owned column
 constexpr int kBwdWarm = 17;    // iterations before the first stored row
 
 struct BwdCtx {
-    const uint8_t* x_plane;    // forward input, float32
-    const uint8_t* gy_plane;   // dL/dU, float32, 2H x 2W
-    uint8_t* gx_plane;         // dL/dV, float32, H x W
-    int64_t x_h, gy_h, gx_h;   // row strides in bytes
-    int32_t x_w, gy_w, gx_w;   // column strides in bytes
+    rsrc_t x, gy, gx;           // one plane each: forward input, dL/dU (2H x 2W), dL/dV (H x W); float32
+    uint32_t x_h, gy_h, gx_h;   // row strides in bytes
+    uint32_t x_w, gy_w, gx_w;   // column strides in bytes
     int32_t H, W;
 };
 
@@ -108,11 +106,6 @@ __device__ __forceinline__ void stencil_adj(float gp, float gs, float g, float d
     gc = __builtin_fmaf(gp, -0.125f, 2.0f * e);
 }
 
-__device__ __forceinline__ float load_f(const uint8_t* plane, int64_t rstride, int r, uint32_t coff)
-{
-    return *(const float*)(plane + (int64_t)r * rstride + coff);
-}
-
 template <int BETA>
 __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
 {
@@ -123,10 +116,10 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     const bool own = lane >= kBwdLane0 && lane < kBwdLane0 + kBwdOwn && J < W;
     const bool colin = J >= 0 && J < W;
     const int jc = J < 0 ? 0 : (J >= W ? W - 1 : J);
-    const uint32_t xoff = (uint32_t)jc * (uint32_t)cx.x_w;
-    const uint32_t gyoffA = (uint32_t)(2 * jc) * (uint32_t)cx.gy_w;        // column 2J
-    const uint32_t gyoffB = (uint32_t)(2 * jc + 1) * (uint32_t)cx.gy_w;    // column 2J+1
-    const uint32_t gxoff = (uint32_t)jc * (uint32_t)cx.gx_w;
+    const uint32_t xoff = (uint32_t)jc * cx.x_w;
+    const uint32_t gyoffA = (uint32_t)(2 * jc) * cx.gy_w;        // column 2J
+    const uint32_t gyoffB = (uint32_t)(2 * jc + 1) * cx.gy_w;    // column 2J+1
+    const uint32_t gxoff = (uint32_t)jc * cx.gx_w;
     const bool first_strip = c0 == 0;
     const bool last_strip = c0 + kBwdOwn >= W;
     const bool top = R0 == 0, bottom = R1 == H;
@@ -134,16 +127,17 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
 
     auto ldV = [&](int r) {
         const int rc = r < 0 ? 0 : (r >= H ? H - 1 : r);
-        return load_f(cx.x_plane, cx.x_h, rc, xoff);
+        return buf_ld_f32(cx.x, xoff, (uint32_t)rc * cx.x_h);
     };
     auto ldG = [&](int r, uint32_t off) {   // dL/dU element, 0 outside the 2H x 2W grid
         float v = 0.0f;
         if (r >= 0 && r < 2 * H) {
-            const float t = load_f(cx.gy_plane, cx.gy_h, r, off);
+            const float t = buf_ld_f32(cx.gy, off, (uint32_t)r * cx.gy_h);
             v = colin ? t : 0.0f;
         }
         return v;
     };
+    auto stG = [&](int r, float val) { buf_st_f32(val, cx.gx, gxoff, (uint32_t)r * cx.gx_h); };
 
     // ---------------- forward state (rows relative to s) ----------------
     float V0 = 0, V1 = 0, V2 = 0, V3 = 0, V4 = 0;       // V(s) .. V(s+4)
@@ -165,7 +159,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     float fold_top = 0, held = 0;
 
     const int s_end = bottom ? H + 7 : R1 + 3;
-    for (int s = R0 - kBwdWarm; s <= s_end; ++s) {
+    auto step = [&](const int s) {
         // ======================= forward =======================
         const float V5 = ldV(s + 5);
         const float dd1_4 = d2(nbL(V3), V4, nbR(V5));
@@ -357,7 +351,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
                 held += (r == H - 1 && top && H == 1) ? val + fold_top : val;
             } else if (r >= R0 && r < R1) {
                 if (top && r == 0) val += fold_top;
-                if (own) *(float*)(cx.gx_plane + (int64_t)r * cx.gx_h + gxoff) = val;
+                if (own) stG(r, val);
             }
         }
 
@@ -378,10 +372,17 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         geoA_gv = nA_gv; geoA_ddd = nA_ddd; geoA_ddu = nA_ddu; geoA_gh = nA_gh; geoA_ddr = nA_ddr; geoA_ddl = nA_ddl;
         accX_m2 = accX_m1; accX_m1 = accX_0; accX_0 = accX_p1;
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
+    };
+    // two rows per trip so that values carried one row are renamed rather than copied
+    int s = R0 - kBwdWarm;
+    for (; s + 1 <= s_end; s += 2) {
+        step(s);
+        step(s + 1);
     }
+    if (s <= s_end) step(s);
     if (bottom) {
         const int r = H - 1;
-        if (r >= R0 && own) *(float*)(cx.gx_plane + (int64_t)r * cx.gx_h + gxoff) = held;
+        if (r >= R0 && own) stG(r, held);
     }
 }
 

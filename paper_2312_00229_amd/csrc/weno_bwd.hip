@@ -10,20 +10,33 @@ using namespace wz;
 
 namespace {
 
+// launch arguments: plane bases and extents (the kernel builds buffer resources per plane)
+struct BwdArgs {
+    const uint8_t* x_base;
+    const uint8_t* gy_base;
+    uint8_t* gx_base;
+    uint32_t x_extent, gy_extent, gx_extent;
+    uint32_t x_h, gy_h, gx_h, x_w, gy_w, gx_w;
+    int32_t H, W;
+};
+
 template <int BETA>
-__global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdCtx base, int C, int64_t x_n, int64_t x_c,
+__global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C, int64_t x_n, int64_t x_c,
                                                             int64_t gy_n, int64_t gy_c, int64_t gx_n, int64_t gx_c,
                                                             int strips_x, int strips_y, int rows, FwdParams P)
 {
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     if (wave >= strips_x * strips_y) return;  // whole wave
     const int plane = blockIdx.y;
     const int n = plane / C, c = plane - n * C;
     const int sy = wave / strips_x, sx = wave - sy * strips_x;
-    BwdCtx cx = base;
-    cx.x_plane += n * x_n + c * x_c;
-    cx.gy_plane += n * gy_n + c * gy_c;
-    cx.gx_plane += n * gx_n + c * gx_c;
+    BwdCtx cx;
+    cx.x = make_rsrc(base.x_base + n * x_n + c * x_c, base.x_extent);
+    cx.gy = make_rsrc(base.gy_base + n * gy_n + c * gy_c, base.gy_extent);
+    cx.gx = make_rsrc(base.gx_base + n * gx_n + c * gx_c, base.gx_extent);
+    cx.x_h = base.x_h; cx.gy_h = base.gy_h; cx.gx_h = base.gx_h;
+    cx.x_w = base.x_w; cx.gy_w = base.gy_w; cx.gx_w = base.gx_w;
+    cx.H = base.H; cx.W = base.W;
     const int R0 = sy * rows;
     const int R1 = min(R0 + rows, cx.H);
     bwd_strip<BETA>(cx, P, sx, R0, R1);
@@ -49,26 +62,35 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
         return WENO_EINVAL;
     if (grad_x->n != x->n || grad_x->c != x->c || grad_x->h != x->h || grad_x->w != x->w) return WENO_EINVAL;
     if ((int64_t)x->n * x->c > 65535) return WENO_EINVAL;
-    if ((int64_t)x->w * x->sw * 4 >= (1ll << 31) || (int64_t)grad_y->w * grad_y->sw * 4 >= (1ll << 31) ||
-        (int64_t)grad_x->w * grad_x->sw * 4 >= (1ll << 31))
+    if (wz_plane_extent(x) >= (1ll << 31) || wz_plane_extent(grad_y) >= (1ll << 31) ||
+        wz_plane_extent(grad_x) >= (1ll << 31))
         return WENO_EINVAL;
     if (wz_overlap(grad_x, x) || wz_overlap(grad_x, grad_y)) return WENO_EOVERLAP;
 
-    const int rows = 64;
-    BwdCtx cx;
-    cx.x_plane = (const uint8_t*)x->data;
-    cx.gy_plane = (const uint8_t*)grad_y->data;
-    cx.gx_plane = (uint8_t*)grad_x->data;
-    cx.x_h = x->sh * 4;
-    cx.gy_h = grad_y->sh * 4;
-    cx.gx_h = grad_x->sh * 4;
-    cx.x_w = (int32_t)(x->sw * 4);
-    cx.gy_w = (int32_t)(grad_y->sw * 4);
-    cx.gx_w = (int32_t)(grad_x->sw * 4);
+    BwdArgs cx;
+    cx.x_base = (const uint8_t*)x->data;
+    cx.gy_base = (const uint8_t*)grad_y->data;
+    cx.gx_base = (uint8_t*)grad_x->data;
+    cx.x_extent = (uint32_t)wz_plane_extent(x);
+    cx.gy_extent = (uint32_t)wz_plane_extent(grad_y);
+    cx.gx_extent = (uint32_t)wz_plane_extent(grad_x);
+    cx.x_h = (uint32_t)(x->sh * 4);
+    cx.gy_h = (uint32_t)(grad_y->sh * 4);
+    cx.gx_h = (uint32_t)(grad_x->sh * 4);
+    cx.x_w = (uint32_t)(x->sw * 4);
+    cx.gy_w = (uint32_t)(grad_y->sw * 4);
+    cx.gx_w = (uint32_t)(grad_x->sw * 4);
     cx.H = x->h;
     cx.W = x->w;
     const FwdParams P = wz_fwd_params(p, 0, 0);
     const int strips_x = (x->w + kBwdOwn - 1) / kBwdOwn;
+    // tallest strip (the walk fills a 21-row pipeline) that still gives ~1500 waves
+    int rows = 16;
+    static const int cand[] = {256, 128, 96, 64, 32, 16};
+    for (int k = 0; k < 6; ++k) {
+        rows = cand[k];
+        if ((int64_t)x->n * x->c * strips_x * ((x->h + rows - 1) / rows) >= 1536) break;
+    }
     const int strips_y = (x->h + rows - 1) / rows;
     dim3 grid((strips_x * strips_y + kWavesPerBlock - 1) / kWavesPerBlock, x->n * x->c);
     hipStream_t st = (hipStream_t)hip_stream;

@@ -58,6 +58,7 @@ struct FwdJob {
     int32_t in_u8, out_u8;            // element types
     int32_t strips_x, strips_y;       // strips per plane
     int32_t vec;                      // 2: float4 rows, 1: float2 rows, 0: scalar stores
+    uint32_t src_extent, dst_extent;  // bytes spanned by one plane (< 2^31)
     int32_t pad_;
 };
 
@@ -132,11 +133,53 @@ struct StripState {
     float Q0[COLS], Q1[COLS];
 };
 
+// Buffer resources (gfx9 family descriptor, raw addressing): the plane base
+// and its byte extent sit in SGPRs, the per-lane column offset in a VGPR and
+// the uniform row offset in an SGPR, so loads and stores need no VALU address
+// arithmetic.  Offsets are 32-bit: the host rejects planes spanning 2^31 bytes
+// or more.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float buf_ld_f32(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ float buf_ld_u8(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return (float)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st_f32(float v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st_f32x2(float a, float b, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 v = {__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st_f32x4(float a, float b, float c, float d, rsrc_t r, uint32_t voff,
+                                             uint32_t soff)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v = {__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b), __builtin_bit_cast(uint32_t, c),
+               __builtin_bit_cast(uint32_t, d)};
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st_u8(uint32_t v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, (int)voff, (int)soff, 0);
+}
+
 struct StripCtx {
-    const uint8_t* src_plane;
-    uint8_t* dst_plane;
-    int64_t s_h, d_h, d_w;
-    int32_t s_w_bytes;
+    rsrc_t src, dst;          // one plane each
+    uint32_t s_h, d_h, d_w;   // byte strides: source rows, destination rows, destination columns
+    uint32_t s_w_bytes;       // source column stride
     int32_t H, W;
     int32_t in_u8, out_u8, vec;
     float out_scale;
@@ -145,14 +188,14 @@ struct StripCtx {
 template <int COLS>
 __device__ __forceinline__ void load_row(const StripCtx& cx, const uint32_t (&off)[COLS], int r, float (&v)[COLS])
 {
-    int rc = r < 0 ? 0 : (r >= cx.H ? cx.H - 1 : r);
-    const uint8_t* rowp = cx.src_plane + (int64_t)rc * cx.s_h;
+    const int rc = r < 0 ? 0 : (r >= cx.H ? cx.H - 1 : r);
+    const uint32_t soff = (uint32_t)rc * cx.s_h;
     if (cx.in_u8) {
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) v[c] = (float)rowp[off[c]];
+        for (int c = 0; c < COLS; ++c) v[c] = buf_ld_u8(cx.src, off[c], soff);
     } else {
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) v[c] = *(const float*)(rowp + off[c]);
+        for (int c = 0; c < COLS; ++c) v[c] = buf_ld_f32(cx.src, off[c], soff);
     }
 }
 
@@ -170,36 +213,36 @@ __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int
                                             const float (&o01)[COLS], const float (&o10)[COLS],
                                             const float (&o11)[COLS])
 {
-    uint8_t* r0 = cx.dst_plane + (int64_t)(2 * R) * cx.d_h;
-    uint8_t* r1 = r0 + cx.d_h;
+    const uint32_t r0 = (uint32_t)(2 * R) * cx.d_h;
+    const uint32_t r1 = r0 + cx.d_h;
     if (!cx.out_u8 && cx.out_scale == 1.0f && COLS == 2 && cx.vec == 2 && own_all) {
         // same dtype in and out: no rescaling
-        uint32_t off = (uint32_t)(2 * J[0]) * 4u;
-        *(float4*)(r0 + off) = make_float4(o00[0], o01[0], o00[COLS - 1], o01[COLS - 1]);
-        *(float4*)(r1 + off) = make_float4(o10[0], o11[0], o10[COLS - 1], o11[COLS - 1]);
+        const uint32_t off = (uint32_t)(2 * J[0]) * 4u;
+        buf_st_f32x4(o00[0], o01[0], o00[COLS - 1], o01[COLS - 1], cx.dst, off, r0);
+        buf_st_f32x4(o10[0], o11[0], o10[COLS - 1], o11[COLS - 1], cx.dst, off, r1);
     } else if (!cx.out_u8) {
         const float s = cx.out_scale;
         if (COLS == 2 && cx.vec == 2 && own_all) {
-            uint32_t off = (uint32_t)(2 * J[0]) * 4u;
-            *(float4*)(r0 + off) = make_float4(o00[0] * s, o01[0] * s, o00[COLS - 1] * s, o01[COLS - 1] * s);
-            *(float4*)(r1 + off) = make_float4(o10[0] * s, o11[0] * s, o10[COLS - 1] * s, o11[COLS - 1] * s);
+            const uint32_t off = (uint32_t)(2 * J[0]) * 4u;
+            buf_st_f32x4(o00[0] * s, o01[0] * s, o00[COLS - 1] * s, o01[COLS - 1] * s, cx.dst, off, r0);
+            buf_st_f32x4(o10[0] * s, o11[0] * s, o10[COLS - 1] * s, o11[COLS - 1] * s, cx.dst, off, r1);
         } else if (cx.vec >= 1) {
 #pragma unroll
             for (int c = 0; c < COLS; ++c) {
                 if (!own[c]) continue;
-                uint32_t off = (uint32_t)(2 * J[c]) * 4u;
-                *(float2*)(r0 + off) = make_float2(o00[c] * s, o01[c] * s);
-                *(float2*)(r1 + off) = make_float2(o10[c] * s, o11[c] * s);
+                const uint32_t off = (uint32_t)(2 * J[c]) * 4u;
+                buf_st_f32x2(o00[c] * s, o01[c] * s, cx.dst, off, r0);
+                buf_st_f32x2(o10[c] * s, o11[c] * s, cx.dst, off, r1);
             }
         } else {
 #pragma unroll
             for (int c = 0; c < COLS; ++c) {
                 if (!own[c]) continue;
-                int64_t off0 = (int64_t)(2 * J[c]) * cx.d_w;
-                *(float*)(r0 + off0) = o00[c] * s;
-                *(float*)(r0 + off0 + cx.d_w) = o01[c] * s;
-                *(float*)(r1 + off0) = o10[c] * s;
-                *(float*)(r1 + off0 + cx.d_w) = o11[c] * s;
+                const uint32_t off0 = (uint32_t)(2 * J[c]) * cx.d_w;
+                buf_st_f32(o00[c] * s, cx.dst, off0, r0);
+                buf_st_f32(o01[c] * s, cx.dst, off0 + cx.d_w, r0);
+                buf_st_f32(o10[c] * s, cx.dst, off0, r1);
+                buf_st_f32(o11[c] * s, cx.dst, off0 + cx.d_w, r1);
             }
         }
     } else {
@@ -207,11 +250,11 @@ __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             if (!own[c]) continue;
-            int64_t off0 = (int64_t)(2 * J[c]) * cx.d_w;
-            r0[off0] = (uint8_t)quant_u8(o00[c] * s);
-            r0[off0 + cx.d_w] = (uint8_t)quant_u8(o01[c] * s);
-            r1[off0] = (uint8_t)quant_u8(o10[c] * s);
-            r1[off0 + cx.d_w] = (uint8_t)quant_u8(o11[c] * s);
+            const uint32_t off0 = (uint32_t)(2 * J[c]) * cx.d_w;
+            buf_st_u8(quant_u8(o00[c] * s), cx.dst, off0, r0);
+            buf_st_u8(quant_u8(o01[c] * s), cx.dst, off0 + cx.d_w, r0);
+            buf_st_u8(quant_u8(o10[c] * s), cx.dst, off0, r1);
+            buf_st_u8(quant_u8(o11[c] * s), cx.dst, off0 + cx.d_w, r1);
         }
     }
 }
@@ -400,7 +443,7 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
         own[c] = (sidx_ >= HALO_L) && (sidx_ < HALO_L + OWN) && (J[c] < cx.W);
         own_all = own_all && own[c];
         const int jc = J[c] < 0 ? 0 : (J[c] >= cx.W ? cx.W - 1 : J[c]);
-        off[c] = (uint32_t)jc * (uint32_t)cx.s_w_bytes;
+        off[c] = (uint32_t)jc * cx.s_w_bytes;
     }
 
     StripState<COLS> s;

@@ -56,5 +56,6 @@ int wz_check_params(const weno_params_t* p);
 int wz_check_pair(const weno_tensor_t* src, const weno_tensor_t* dst, int factor);
 void wz_byte_range(const weno_tensor_t* t, uintptr_t* lo, uintptr_t* hi);
 bool wz_overlap(const weno_tensor_t* a, const weno_tensor_t* b);
+int64_t wz_plane_extent(const weno_tensor_t* t);
 double wz_nbw(const weno_params_t* p);
 int wz_beta_mode(float beta);

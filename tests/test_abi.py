@@ -126,9 +126,10 @@ def test_launch_config_validation():
     L = _lib.lib()
     r, c = ctypes.c_int32(), ctypes.c_int32()
     L.weno_get_launch_config(ctypes.byref(r), ctypes.byref(c))
-    assert L.weno_set_launch_config(12, 2) == _lib.WENO_EINVAL
+    assert L.weno_set_launch_config(3, 2) == _lib.WENO_EINVAL
     assert L.weno_set_launch_config(64, 3) == _lib.WENO_EINVAL
-    assert L.weno_set_launch_config(2048, 1) == _lib.WENO_EINVAL
+    assert L.weno_set_launch_config(8192, 1) == _lib.WENO_EINVAL
+    assert L.weno_set_launch_config(0, 0) == _lib.WENO_OK
     assert L.weno_set_launch_config(r.value, c.value) == _lib.WENO_OK
 
 

@@ -1,0 +1,55 @@
+"""GPU parity of weno_resample and weno_zoom_to (Section 3.3) against the
+FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import u8_compare
+from oracle import resample as R
+from workloads import pixel_art, random_plane, scene_rgb
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _t(a, dtype=np.float32):
+    return torch.tensor(np.ascontiguousarray(a, dtype=dtype), device="cuda")
+
+
+@pytest.mark.parametrize("shape,out", [((9, 11), (17, 5)), ((40, 70), (100, 33)), ((1, 5), (3, 9)), ((64, 64), (64, 64)),
+                                       ((130, 97), (257, 401)), ((50, 3), (7, 2))])
+@pytest.mark.parametrize("beta", [2.0, 1.0])
+def test_resample_f32(gpu, shape, out, beta):
+    V = random_plane(*shape, seed=shape[0], kind="steps") * 0.6 + 0.4 * random_plane(*shape, seed=1)
+    got = gpu.resample(_t(V), *out, gpu.Params(beta=beta)).cpu().numpy()
+    ref = R.tensor_resample(V.astype(np.float32).astype(np.float64), *out, beta=beta)
+    assert np.abs(got - ref).max() <= TOL
+
+
+def test_resample_u8_hwc(gpu):
+    img = scene_rgb(60, 90, seed=3, n_polygons=8)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    y = gpu.resample(x, 133, 211)
+    ref = R.tensor_resample(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 133, 211)
+    ties, errors = u8_compare(y.cpu().numpy(), ref)
+    assert errors == 0
+
+
+@pytest.mark.parametrize("shape,out", [((7, 9), (13, 17)), ((20, 30), (57, 88)), ((33, 40), (20, 25)),
+                                       ((16, 16), (100, 61))])
+def test_zoom_to_f32(gpu, shape, out):
+    V = random_plane(*shape, seed=7, kind="steps") * 0.5 + 0.5 * random_plane(*shape, seed=8)
+    got = gpu.zoom_to(_t(V), *out).cpu().numpy()
+    ref = R.zoom_to(V.astype(np.float32).astype(np.float64), *out)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= 3 * TOL
+
+
+def test_zoom_to_scale3_pixel_art_u8(gpu):
+    # the paper's scale-3 example: over-zoom to (4n-3) and resample to 3n
+    img = pixel_art(32, 40, seed=6, block=4, n_lines=5)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    y = gpu.zoom_to(x, 96, 120)
+    ref = R.zoom_to(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 96, 120)
+    ties, errors = u8_compare(y.cpu().numpy(), ref, tie_band=3 * TOL)
+    assert errors == 0
