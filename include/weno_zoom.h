@@ -198,7 +198,9 @@ int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, co
  * two waves per SIMD of the device.  The configuration changes speed only: every
  * configuration produces bit-identical outputs.  Batched plans capture the
  * configuration when they are made (automatic: 32 rows, 2 columns).
- * weno_get_launch_config reports (0, 0) in automatic mode.
+ * weno_get_launch_config reports (0, 0) in automatic mode.  An explicit
+ * rows_per_strip also sets the strip height of the adjoint kernel (which
+ * always uses one column per lane; automatic: two equal waves per SIMD).
  * Returns WENO_EINVAL for values outside these sets.
  */
 int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane);

@@ -44,9 +44,17 @@ __device__ __forceinline__ StripCtx make_ctx(const FwdJob& jb, int n, int c, flo
 template <int COLS, int BETA>
 __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
 {
+    // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+    // Renumber them so that every XCD gets a contiguous range of strips
+    // (whole bands of adjacent rows): the 9 halo rows a strip shares with the
+    // strip above are then re-read from the same L2.  A bijection on
+    // [0, gridDim.x).
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int xcd = b % kXcds, k = b / kXcds;
+    const int logical = xcd * (nb / kXcds) + min(xcd, nb % kXcds) + k;
     // the wave index is the same in every lane; say so, so that strip rows and
     // buffer offsets live in SGPRs
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(logical * kWavesPerBlock + (threadIdx.x >> 6));
     const int per_plane = jb.strips_x * jb.strips_y;
     if (wave >= per_plane) return;  // whole wave
     const int plane = blockIdx.y;
@@ -178,6 +186,8 @@ extern "C" void weno_get_launch_config(int32_t* rows_per_strip, int32_t* cols_pe
 // validation helpers (shared with the adjoint and the cascade)
 // --------------------------------------------------------------------------
 int wz_esize(int32_t dtype) { return dtype == WENO_U8 ? 1 : (dtype == WENO_F32 ? 4 : 0); }
+
+int wz_explicit_rows() { return g_rows_per_strip.load(); }
 
 int wz_check_tensor(const weno_tensor_t* t)
 {
@@ -344,7 +354,7 @@ void wz_auto_config(int64_t planes, int H, int W, int* rows, int* cols)
     const int own = c == 1 ? kWave - 9 : 2 * kWave - 10;
     const int64_t columns = planes * ((W + own - 1) / own);
     const int64_t target = 2 * (int64_t)device_simds();
-    int64_t bands = (target + columns / 2) / columns;
+    int64_t bands = target / columns;  // never more waves than two per SIMD: no tail round
     if (bands < 1) bands = 1;
     int r = (int)((H + bands - 1) / bands);
     r = r < 8 ? 8 : (r > 64 ? 64 : r);

@@ -84,13 +84,21 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     cx.W = x->w;
     const FwdParams P = wz_fwd_params(p, 0, 0);
     const int strips_x = (x->w + kBwdOwn - 1) / kBwdOwn;
-    // tallest strip (the walk fills a 21-row pipeline) that still gives ~1500 waves
-    int rows = 16;
-    static const int cand[] = {256, 128, 96, 64, 32, 16};
-    for (int k = 0; k < 6; ++k) {
-        rows = cand[k];
-        if ((int64_t)x->n * x->c * strips_x * ((x->h + rows - 1) / rows) >= 1536) break;
-    }
+    // Bands give about four waves per SIMD (two resident at a time, 232
+    // registers each): measured on 16 x 3 x 512^2, two rounds of waves beat a
+    // single round of twice-as-tall strips (0.70 ms at 96 rows vs 1.0 ms at
+    // 171), and strips shorter than 32 rows pay too much for the 21-row
+    // pipeline fill.
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int64_t columns = (int64_t)x->n * x->c * strips_x;
+    const int64_t target = 4 * 4 * (int64_t)cus;
+    int64_t bands = target / columns;
+    if (bands < 1) bands = 1;
+    int rows = (int)((x->h + bands - 1) / bands);
+    if (rows < 32) rows = 32;
+    if (wz_explicit_rows() > 0) rows = wz_explicit_rows();
     const int strips_y = (x->h + rows - 1) / rows;
     dim3 grid((strips_x * strips_y + kWavesPerBlock - 1) / kWavesPerBlock, x->n * x->c);
     hipStream_t st = (hipStream_t)hip_stream;

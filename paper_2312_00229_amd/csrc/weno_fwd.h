@@ -37,6 +37,7 @@ namespace wz {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kXcds = 8;  // MI355X: accelerator complex dies, one L2 each
 
 // beta specialisations
 constexpr int kBetaGeneral = -1;

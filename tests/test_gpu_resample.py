@@ -53,3 +53,18 @@ def test_zoom_to_scale3_pixel_art_u8(gpu):
     ref = R.zoom_to(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 96, 120)
     ties, errors = u8_compare(y.cpu().numpy(), ref, tie_band=3 * TOL)
     assert errors == 0
+
+
+def test_quality_protocol_runs(gpu):
+    # the paper's crop / downsample / upsample protocol: nested-grid nodes of
+    # the WD-WENO result are the downsampled samples themselves
+    import quality
+    from workloads import to_planar_f32
+
+    img = torch.tensor(to_planar_f32(scene_rgb(129, 193, seed=11, n_polygons=10)), device="cuda")
+    res = quality.protocol(img, 2)
+    assert set(res) == {"wd_weno", "tensor_weno", "bicubic", "bilinear"}
+    for p, s in res.values():
+        assert 10.0 < p < 80.0 and 0.0 < s <= 1.0
+    up = gpu.zoom_to(img[:, ::2, ::2].contiguous(), 129, 193)
+    assert torch.equal(up[:, ::2, ::2], img[:, ::2, ::2])
