@@ -200,7 +200,9 @@ int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, co
  * configuration when they are made (automatic: 32 rows, 2 columns).
  * weno_get_launch_config reports (0, 0) in automatic mode.  An explicit
  * rows_per_strip also sets the strip height of the adjoint kernel (which
- * always uses one column per lane; automatic: two equal waves per SIMD).
+ * always uses one column per lane; automatic: the height that minimises the
+ * rounds of resident waves times the rows each wave walks), whose results are
+ * also bit-identical across strip heights.
  * Returns WENO_EINVAL for values outside these sets.
  */
 int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane);

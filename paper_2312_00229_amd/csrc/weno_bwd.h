@@ -30,8 +30,12 @@
 //   output      dL/dV row s-4 is complete: fold clamped rows/columns onto the
 //               edge pixels and store.
 // Valid lanes shrink with every neighbour access: the dL/dV of lanes 9..54 is
-// exact, so a strip owns 38 columns at lanes 13..50 and the four padded
-// columns on either side of the image fall in lanes 9..12 / 51..54.
+// exact.  A strip owns up to 42 columns: the first strip of a row starts at
+// lane 13 so that the four padded columns left of the image (folded onto
+// column 0) fall in lanes 9..12; the others start at lane 9, which leaves
+// lanes up to 54 for the four padded columns right of the image in the last
+// strip.  A strip that is both first and last holds at most 38 columns, so
+// images 39..42 wide are split into two strips of 21.
 #pragma once
 
 #include <stdint.h>
@@ -40,9 +44,22 @@
 
 namespace wz {
 
-constexpr int kBwdOwn = 38;     // columns stored per strip
-constexpr int kBwdLane0 = 13;   // lane of the strip's first owned column
-constexpr int kBwdWarm = 17;    // iterations before the first stored row
+constexpr int kBwdOwn = 42;        // columns stored per strip
+constexpr int kBwdLane0First = 13; // lane of the first owned column, first strip of a row
+constexpr int kBwdLane0 = 9;       // lane of the first owned column, other strips
+
+// columns per strip for an image W wide (host and device)
+__host__ __device__ inline int bwd_strip_width(int W) { return (W >= 39 && W <= 42) ? 21 : kBwdOwn; }
+
+// Iterations before the first exact dL/dV row.  A walk that starts at row a
+// (windows holding fill values) has exact V rows from a+5, second differences
+// and x-point indicators from a+6, x-point blends from a+7, +-point blends
+// from a+9, their adjoint from a+10, complete dL/dx rows from a+11 and the
+// x-point adjoint from a+15; that last one feeds dL/dV rows r-1 .. r+2, so
+// the first exact dL/dV row is a+14.  The top strip also folds the padded
+// rows -4..-1 onto row 0, so it starts 4 rows earlier.
+constexpr int kBwdWarm = 14;
+constexpr int kBwdWarmTop = 18;
 
 struct BwdCtx {
     rsrc_t x, gy, gx;           // one plane each: forward input, dL/dU (2H x 2W), dL/dV (H x W); float32
@@ -110,10 +127,12 @@ template <int BETA>
 __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int c0 = strip_x * kBwdOwn;
-    const int J = c0 - kBwdLane0 + lane;
     const int H = cx.H, W = cx.W;
-    const bool own = lane >= kBwdLane0 && lane < kBwdLane0 + kBwdOwn && J < W;
+    const int width = bwd_strip_width(W);
+    const int c0 = strip_x * width;
+    const int lane0 = strip_x == 0 ? kBwdLane0First : kBwdLane0;
+    const int J = c0 - lane0 + lane;
+    const bool own = lane >= lane0 && lane < lane0 + width && J < W;
     const bool colin = J >= 0 && J < W;
     const int jc = J < 0 ? 0 : (J >= W ? W - 1 : J);
     const uint32_t xoff = (uint32_t)jc * cx.x_w;
@@ -121,7 +140,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     const uint32_t gyoffB = (uint32_t)(2 * jc + 1) * cx.gy_w;    // column 2J+1
     const uint32_t gxoff = (uint32_t)jc * cx.gx_w;
     const bool first_strip = c0 == 0;
-    const bool last_strip = c0 + kBwdOwn >= W;
+    const bool last_strip = c0 + width >= W;
     const bool top = R0 == 0, bottom = R1 == H;
     const float eh = P.eps_hat, w = P.w, beta = P.beta;
 
@@ -374,7 +393,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
     };
     // two rows per trip so that values carried one row are renamed rather than copied
-    int s = R0 - kBwdWarm;
+    int s = R0 - (top ? kBwdWarmTop : kBwdWarm);
     for (; s + 1 <= s_end; s += 2) {
         step(s);
         step(s + 1);

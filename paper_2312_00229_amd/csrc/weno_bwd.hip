@@ -2,6 +2,9 @@
 // in weno_bwd.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <cstdint>
+
 #include "weno_bwd.h"
 #include "weno_internal.h"
 #include "weno_zoom.h"
@@ -40,6 +43,53 @@ __global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C,
     const int R0 = sy * rows;
     const int R1 = min(R0 + rows, cx.H);
     bwd_strip<BETA>(cx, P, sx, R0, R1);
+}
+
+// Blocks of the adjoint kernel resident on the whole device at once (its
+// register use allows two waves per SIMD, i.e. two blocks per CU).
+int64_t bwd_resident_blocks()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
+    int v = cache[dev].load();
+    if (v == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(zoom2x_bwd_kernel<2>),
+                                                         kBlock, 0) != hipSuccess || per_cu <= 0)
+            per_cu = 1;
+        v = cus * per_cu;
+        cache[dev].store(v);
+    }
+    return v;
+}
+
+// Strip height of the adjoint.  Every strip walks rows + kBwdWarm steps and
+// all strips take the same time, so a launch costs about
+//   (rounds of resident blocks) x (rows + kBwdWarm);
+// the band count that minimises it wins (the fewest bands on a tie).  The
+// best launches fill the device just short of a whole number of rounds with
+// the tallest strips that allows.
+int bwd_auto_rows(int H, int strips_x, int64_t planes, int64_t resident)
+{
+    int best_rows = H;
+    int64_t best = INT64_MAX;
+    const int max_b = H < 1024 ? H : 1024;
+    for (int b = 1; b <= max_b; ++b) {
+        const int rows = (H + b - 1) / b;
+        if (b > 1 && rows < 4) break;   // one band always qualifies
+        const int bands = (H + rows - 1) / rows;
+        if (bands != b) continue;   // same strips as a smaller band count
+        const int64_t blocks = planes * (((int64_t)strips_x * bands + kWavesPerBlock - 1) / kWavesPerBlock);
+        const int64_t rounds = (blocks + resident - 1) / resident;
+        const int64_t cost = rounds * (rows + kBwdWarm);
+        if (cost < best) {
+            best = cost;
+            best_rows = rows;
+        }
+    }
+    return best_rows;
 }
 
 }  // namespace
@@ -83,21 +133,9 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     cx.H = x->h;
     cx.W = x->w;
     const FwdParams P = wz_fwd_params(p, 0, 0);
-    const int strips_x = (x->w + kBwdOwn - 1) / kBwdOwn;
-    // Bands give about four waves per SIMD (two resident at a time, 232
-    // registers each): measured on 16 x 3 x 512^2, two rounds of waves beat a
-    // single round of twice-as-tall strips (0.70 ms at 96 rows vs 1.0 ms at
-    // 171), and strips shorter than 32 rows pay too much for the 21-row
-    // pipeline fill.
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    const int64_t columns = (int64_t)x->n * x->c * strips_x;
-    const int64_t target = 4 * 4 * (int64_t)cus;
-    int64_t bands = target / columns;
-    if (bands < 1) bands = 1;
-    int rows = (int)((x->h + bands - 1) / bands);
-    if (rows < 32) rows = 32;
+    const int strips_x = (x->w + bwd_strip_width(x->w) - 1) / bwd_strip_width(x->w);
+    const int64_t planes = (int64_t)x->n * x->c;
+    int rows = bwd_auto_rows(x->h, strips_x, planes, bwd_resident_blocks());
     if (wz_explicit_rows() > 0) rows = wz_explicit_rows();
     const int strips_y = (x->h + rows - 1) / rows;
     dim3 grid((strips_x * strips_y + kWavesPerBlock - 1) / kWavesPerBlock, x->n * x->c);

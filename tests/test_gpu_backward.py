@@ -29,7 +29,9 @@ def _close(got, ref):
     return np.abs(got - ref).max() <= RTOL * max(1.0, np.abs(ref).max())
 
 
-SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (7, 77), (40, 39), (65, 120), (130, 37), (64, 38), (3, 200)]
+SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (7, 77), (40, 39), (65, 120), (130, 37), (64, 38), (3, 200),
+          # strip-width boundaries: one strip up to 38 columns, two of 21 for 39..42, then 42 per strip
+          (6, 42), (5, 43), (11, 84), (9, 85), (12, 126), (7, 127)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -80,6 +82,21 @@ def test_backward_deterministic(gpu):
     a = gpu.zoom2x_backward(x, g)
     b = gpu.zoom2x_backward(x, g)
     assert torch.equal(a, b)
+
+
+def test_backward_independent_of_strip_height(gpu):
+    """Every strip recomputes its warm-up rows exactly, so the result does not
+    depend on where the bands start: bit-identical for every strip height."""
+    rng = np.random.default_rng(15)
+    x = _t(rng.random((2, 150, 100)))
+    g = _t(rng.standard_normal((2, 300, 200)))
+    ref = gpu.zoom2x_backward(x, g)
+    try:
+        for rows in (4, 5, 8, 13, 32, 64, 149):
+            gpu.set_launch_config(rows, 1)
+            assert torch.equal(gpu.zoom2x_backward(x, g), ref), rows
+    finally:
+        gpu.set_launch_config(0, 0)
 
 
 def test_autograd_function(gpu):
