@@ -136,8 +136,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     const bool colin = J >= 0 && J < W;
     const int jc = J < 0 ? 0 : (J >= W ? W - 1 : J);
     const uint32_t xoff = (uint32_t)jc * cx.x_w;
-    const uint32_t gyoffA = (uint32_t)(2 * jc) * cx.gy_w;        // column 2J
-    const uint32_t gyoffB = (uint32_t)(2 * jc + 1) * cx.gy_w;    // column 2J+1
+    // dL/dU outside the 2H x 2W grid counts as 0: lanes outside the image and
+    // rows outside it read through an offset past the end of the buffer, which
+    // the buffer unit answers with 0 and no memory access, so the loads need no
+    // branch and can be issued a step before their use
+    constexpr uint32_t kOob = 0x80000000u;   // above every plane extent (< 2^31)
+    const uint32_t gyoffA = colin ? (uint32_t)(2 * jc) * cx.gy_w : kOob;        // column 2J
+    const uint32_t gyoffB = colin ? (uint32_t)(2 * jc + 1) * cx.gy_w : kOob;    // column 2J+1
     const uint32_t gxoff = (uint32_t)jc * cx.gx_w;
     const bool first_strip = c0 == 0;
     const bool last_strip = c0 + width >= W;
@@ -149,16 +154,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         return buf_ld_f32(cx.x, xoff, (uint32_t)rc * cx.x_h);
     };
     auto ldG = [&](int r, uint32_t off) {   // dL/dU element, 0 outside the 2H x 2W grid
-        float v = 0.0f;
-        if (r >= 0 && r < 2 * H) {
-            const float t = buf_ld_f32(cx.gy, off, (uint32_t)r * cx.gy_h);
-            v = colin ? t : 0.0f;
-        }
-        return v;
+        const bool in = r >= 0 && r < 2 * H;
+        return buf_ld_f32(cx.gy, in ? off : kOob, in ? (uint32_t)r * cx.gy_h : 0u);
     };
     auto stG = [&](int r, float val) { buf_st_f32(val, cx.gx, gxoff, (uint32_t)r * cx.gx_h); };
 
     // ---------------- forward state (rows relative to s) ----------------
+    float Vm4 = 0, Vm3 = 0, Vm2 = 0, Vm1 = 0;           // V(s-4) .. V(s-1)
     float V0 = 0, V1 = 0, V2 = 0, V3 = 0, V4 = 0;       // V(s) .. V(s+4)
     float dd1_3 = 0, dd2s_3 = 0;
     // indicator windows start at 1 so that pipeline-fill blends never divide by zero
@@ -178,9 +180,21 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     float fold_top = 0, held = 0;
 
     const int s_end = bottom ? H + 7 : R1 + 3;
+    int s = R0 - (top ? kBwdWarmTop : kBwdWarm);
+    // loads run ahead of their use: V two rows, dL/dU one step
+    float Q0 = ldV(s + 5), Q1 = ldV(s + 6);
+    float nA = ldG(2 * s + 1, gyoffA), nB = ldG(2 * s, gyoffB);             // + point seeds of row s
+    float nX = ldG(2 * s - 3, gyoffB), nV = ldG(2 * s - 8, gyoffA);         // x row s-2, V row s-4
     auto step = [&](const int s) {
+        const float V5 = Q0;
+        Q0 = Q1;
+        Q1 = ldV(s + 7);
+        const float gA = nA, gB = nB, gXu = nX, gVu = nV;
+        nA = ldG(2 * s + 3, gyoffA);
+        nB = ldG(2 * s + 2, gyoffB);
+        nX = ldG(2 * s - 1, gyoffB);
+        nV = ldG(2 * s - 6, gyoffA);
         // ======================= forward =======================
-        const float V5 = ldV(s + 5);
         const float dd1_4 = d2(nbL(V3), V4, nbR(V5));
         const float dd2_4 = d2(nbR(V3), V4, nbL(V5));
         const float dd1s_4 = nbR(dd1_4), dd2s_4 = nbR(dd2_4);
@@ -255,8 +269,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= phase-2 seeds =======================
-        const float gA = ldG(2 * s + 1, gyoffA);
-        const float gB = ldG(2 * s, gyoffB);
         float gtA[4], gpA[4], gtB[4], gpB[4], qA[4], qB[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -313,7 +325,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= phase-1 seeds at x row s-2 =======================
-        const float gXc = accX_m2 + ldG(2 * (s - 2) + 1, gyoffB);
+        const float gXc = accX_m2 + gXu;
         float gtX_m2[4], gpX_m2[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -323,7 +335,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
 
         // ======================= phase-1 adjoint at x row r = s-3 =======================
         {
-            const float Pv = ldV(s - 4), Qv = ldV(s - 3), Rv = ldV(s - 2), Tv = ldV(s - 1);
+            const float Pv = Vm4, Qv = Vm3, Rv = Vm2, Tv = Vm1;
             const float dd1_r = d2(nbL(Pv), Qv, nbR(Rv));
             const float dd1s_r1 = nbR(d2(nbL(Qv), Rv, nbR(Tv)));
             const float dd2s_r = nbR(d2(nbR(Pv), Qv, nbL(Rv)));
@@ -349,7 +361,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         // ======================= dL/dV row s-4 is complete =======================
         {
             const int r = s - 4;
-            float val = accV_m4 + ldG(2 * r, gyoffA);
+            float val = accV_m4 + gVu;
             // clamped columns: padded columns -4..-1 fold onto column 0, W..W+3 onto W-1
             if (first_strip) {
                 float p = J < 0 ? val : 0.0f, acc = 0.0f;
@@ -375,6 +387,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= slide the windows =======================
+        Vm4 = Vm3; Vm3 = Vm2; Vm2 = Vm1; Vm1 = V0;
         V0 = V1; V1 = V2; V2 = V3; V3 = V4; V4 = V5;
         dd1_3 = dd1_4; dd2s_3 = dd2s_4;
         X0 = X1; X1 = X2; ddXv0 = ddXv1; ddr0 = ddr1;
@@ -393,7 +406,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
     };
     // two rows per trip so that values carried one row are renamed rather than copied
-    int s = R0 - (top ? kBwdWarmTop : kBwdWarm);
     for (; s + 1 <= s_end; s += 2) {
         step(s);
         step(s + 1);
