@@ -41,7 +41,7 @@ __device__ __forceinline__ StripCtx make_ctx(const FwdJob& jb, int n, int c, flo
     return cx;
 }
 
-template <int COLS, int BETA>
+template <int COLS, int BETA, int IO>
 __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
 {
     // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, 
     const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
     const int R0 = sy * rows_per_strip;
     const int R1 = min(R0 + rows_per_strip, jb.H);
-    zoom_strip<COLS, BETA>(cx, P, sx, R0, R1);
+    zoom_strip<COLS, BETA, IO>(cx, P, sx, R0, R1);
 }
 
 // Persistent kernel over a work queue of strips of many images.  Item i of
@@ -110,7 +110,9 @@ __global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable
         const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
         const int R0 = sy * rows_per_strip;
         const int R1 = min(R0 + rows_per_strip, jb.H);
-        zoom_strip<COLS, BETA>(cx, P, sx, R0, R1);
+        if (jb.io == kIoF32) zoom_strip<COLS, BETA, kIoF32>(cx, P, sx, R0, R1);
+        else if (jb.io == kIoU8) zoom_strip<COLS, BETA, kIoU8>(cx, P, sx, R0, R1);
+        else zoom_strip<COLS, BETA, kIoGeneric>(cx, P, sx, R0, R1);
     }
 }
 
@@ -291,6 +293,9 @@ FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols,
         vec = a16 ? 2 : (a8 ? 1 : 0);
     }
     jb.vec = vec;
+    if (!jb.in_u8 && !jb.out_u8 && (cols == 2 ? vec == 2 : vec >= 1)) jb.io = kIoF32;
+    else if (jb.in_u8 && jb.out_u8) jb.io = kIoU8;
+    else jb.io = kIoGeneric;
     jb.src_extent = (uint32_t)wz_plane_extent(src);
     jb.dst_extent = (uint32_t)wz_plane_extent(dst);
     return jb;
@@ -312,19 +317,27 @@ int wz_check_pair(const weno_tensor_t* src, const weno_tensor_t* dst, int factor
     return WENO_OK;
 }
 
-template <int COLS>
-static hipError_t launch_fwd_cols(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
+template <int COLS, int IO>
+static hipError_t launch_fwd_io(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
 {
     const int per_plane = jb.strips_x * jb.strips_y;
     dim3 grid((per_plane + kWavesPerBlock - 1) / kWavesPerBlock, jb.planes);
     dim3 block(kBlock);
     if (beta_mode == 2)
-        hipLaunchKernelGGL((zoom2x_kernel<COLS, 2>), grid, block, 0, st, jb, P, rows);
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, 2, IO>), grid, block, 0, st, jb, P, rows);
     else if (beta_mode == 1)
-        hipLaunchKernelGGL((zoom2x_kernel<COLS, 1>), grid, block, 0, st, jb, P, rows);
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, 1, IO>), grid, block, 0, st, jb, P, rows);
     else
-        hipLaunchKernelGGL((zoom2x_kernel<COLS, kBetaGeneral>), grid, block, 0, st, jb, P, rows);
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, kBetaGeneral, IO>), grid, block, 0, st, jb, P, rows);
     return hipGetLastError();
+}
+
+template <int COLS>
+static hipError_t launch_fwd_cols(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
+{
+    if (jb.io == kIoF32) return launch_fwd_io<COLS, kIoF32>(jb, P, beta_mode, rows, st);
+    if (jb.io == kIoU8) return launch_fwd_io<COLS, kIoU8>(jb, P, beta_mode, rows, st);
+    return launch_fwd_io<COLS, kIoGeneric>(jb, P, beta_mode, rows, st);
 }
 
 // SIMDs of the current device (4 per compute unit), cached per device

@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace wz {
 
 constexpr int kWave = 64;
@@ -41,6 +43,19 @@ constexpr int kXcds = 8;  // MI355X: accelerator complex dies, one L2 each
 
 // beta specialisations
 constexpr int kBetaGeneral = -1;
+
+// I/O modes of the strip walk.  The two common layouts are fixed at compile
+// time so that every row issues the same memory operations, with no branch:
+// the compiler can then keep prefetched rows in flight across iterations.
+constexpr int kIoGeneric = 0;  // any dtype pair, strides and output scale (runtime flags)
+constexpr int kIoF32 = 1;      // f32 -> f32, destination columns contiguous and vector-aligned
+constexpr int kIoU8 = 2;       // u8 -> u8, any strides
+
+// A buffer offset past every plane extent (planes span less than 2^31 bytes):
+// loads through it return 0 and stores through it are dropped by the buffer
+// unit's range check, with no memory access.  Row offsets added to it stay
+// below 2^32, so the sum cannot wrap back into range.
+constexpr uint32_t kOob = 0x80000000u;
 
 struct FwdParams {
     float eps_hat;  // see header comment, in the kernel's value scale
@@ -60,7 +75,7 @@ struct FwdJob {
     int32_t strips_x, strips_y;       // strips per plane
     int32_t vec;                      // 2: float4 rows, 1: float2 rows, 0: scalar stores
     uint32_t src_extent, dst_extent;  // bytes spanned by one plane (< 2^31)
-    int32_t pad_;
+    int32_t io;                       // I/O mode (kIo*)
 };
 
 __device__ __forceinline__ float from_left(float x)
@@ -130,8 +145,19 @@ struct StripState {
     float ddXv0[COLS], ddr0[COLS];
     // phase-2: B(R) indicators/candidates, B pair sums at row R, A pair sums at row R-1
     float SB0[4][COLS], PB0[4][COLS], hB0[4][COLS], hAm1[4][COLS];
-    // prefetch queue: input rows R+5 and R+6, loaded two iterations before use
-    float Q0[COLS], Q1[COLS];
+};
+
+// Per-lane geometry of a strip, fixed for the whole walk.
+template <int COLS>
+struct StripLanes {
+    uint32_t src_off[COLS];  // source column byte offsets (columns clamped to the image)
+    int J[COLS];             // input column of each of the lane's columns
+    bool own[COLS];          // column stored by this strip
+    bool own_all;
+    uint32_t st_col[COLS];   // kIoU8: destination column offsets, kOob where not owned
+    uint32_t st_vec;         // kIoF32: offset of the lane's vector store, kOob unless all its columns are owned
+    uint32_t st_half;        // kIoF32, two columns: offset of a 2-float store when only column 0 is owned, else kOob
+    bool any_half;           // some lane of the strip needs st_half (odd width, last strip); uniform
 };
 
 // Buffer resources (gfx9 family descriptor, raw addressing): the plane base
@@ -186,18 +212,42 @@ struct StripCtx {
     float out_scale;
 };
 
-template <int COLS>
-__device__ __forceinline__ void load_row(const StripCtx& cx, const uint32_t (&off)[COLS], int r, float (&v)[COLS])
+// Raw load of input row r (clamped) into a queue slot: f32 bits or a
+// zero-extended byte.  The conversion to float happens when the row is
+// consumed, two iterations later, so no wait follows the load.
+// queue word of an I/O mode: the u8 mode keeps the loaded byte as a byte, so
+// that its widening folds into the conversion at the consuming iteration
+template <int IO>
+using raw_t = typename std::conditional<IO == kIoU8, uint8_t, uint32_t>::type;
+
+template <int COLS, int IO>
+__device__ __forceinline__ void load_row_raw(const StripCtx& cx, const uint32_t (&off)[COLS], int r, raw_t<IO> (&q)[COLS])
 {
     const int rc = r < 0 ? 0 : (r >= cx.H ? cx.H - 1 : r);
     const uint32_t soff = (uint32_t)rc * cx.s_h;
-    if (cx.in_u8) {
+    const bool u8 = IO == kIoU8 || (IO == kIoGeneric && cx.in_u8);
+    if (u8) {
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) v[c] = buf_ld_u8(cx.src, off[c], soff);
+        for (int c = 0; c < COLS; ++c) q[c] = __builtin_amdgcn_raw_buffer_load_b8(cx.src, (int)off[c], (int)soff, 0);
     } else {
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) v[c] = buf_ld_f32(cx.src, off[c], soff);
+        for (int c = 0; c < COLS; ++c) q[c] = __builtin_amdgcn_raw_buffer_load_b32(cx.src, (int)off[c], (int)soff, 0);
     }
+}
+
+template <int IO>
+__device__ __forceinline__ float raw_value(const StripCtx& cx, raw_t<IO> q)
+{
+    if constexpr (IO == kIoU8) return (float)q;
+    else if constexpr (IO == kIoF32) {
+        // an explicit copy into a register of its own: the slot's register is
+        // then free for the row loaded next, so it stays the loop-carried
+        // register and is not copied (waiting for that load) at the back edge
+        float v;
+        asm("v_mov_b32 %0, %1" : "=&v"(v) : "v"(q));
+        return v;
+    }
+    else return cx.in_u8 ? (float)q : __builtin_bit_cast(float, q);
 }
 
 __device__ __forceinline__ uint32_t quant_u8(float u)
@@ -207,7 +257,40 @@ __device__ __forceinline__ uint32_t quant_u8(float u)
     return (uint32_t)q;
 }
 
-// store the 2x2 quads of row R for this lane's columns
+// store the 2x2 quads of row R for this lane's columns: fixed layouts,
+// branch-free (lanes that own nothing store through kOob)
+template <int COLS, int IO>
+__device__ __forceinline__ void store_quads_fixed(const StripCtx& cx, int R, const StripLanes<COLS>& L,
+                                                  const float (&o00)[COLS], const float (&o01)[COLS],
+                                                  const float (&o10)[COLS], const float (&o11)[COLS])
+{
+    const uint32_t r0 = (uint32_t)(2 * R) * cx.d_h;
+    const uint32_t r1 = r0 + cx.d_h;
+    if constexpr (IO == kIoF32) {
+        if constexpr (COLS == 2) {
+            buf_st_f32x4(o00[0], o01[0], o00[1], o01[1], cx.dst, L.st_vec, r0);
+            buf_st_f32x4(o10[0], o11[0], o10[1], o11[1], cx.dst, L.st_vec, r1);
+            if (L.any_half) {
+                buf_st_f32x2(o00[0], o01[0], cx.dst, L.st_half, r0);
+                buf_st_f32x2(o10[0], o11[0], cx.dst, L.st_half, r1);
+            }
+        } else {
+            buf_st_f32x2(o00[0], o01[0], cx.dst, L.st_vec, r0);
+            buf_st_f32x2(o10[0], o11[0], cx.dst, L.st_vec, r1);
+        }
+    } else {  // kIoU8: one byte per output, value scale unchanged
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            const uint32_t off0 = L.st_col[c];
+            buf_st_u8(quant_u8(o00[c]), cx.dst, off0, r0);
+            buf_st_u8(quant_u8(o01[c]), cx.dst, off0 + cx.d_w, r0);
+            buf_st_u8(quant_u8(o10[c]), cx.dst, off0, r1);
+            buf_st_u8(quant_u8(o11[c]), cx.dst, off0 + cx.d_w, r1);
+        }
+    }
+}
+
+// store the 2x2 quads of row R for this lane's columns (any layout)
 template <int COLS>
 __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int (&J)[COLS], bool own_all,
                                             const bool (&own)[COLS], const float (&o00)[COLS],
@@ -260,32 +343,31 @@ __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int
     }
 }
 
-// One strip-walk iteration.  FULL = main loop (every stage runs, quad row R
-// is stored); otherwise a prologue iteration, d = R - R0 < 0, and each
-// stage only runs once its results can feed an output row >= R0.
-template <int COLS, int BETA, bool FULL>
-__device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& cx, const FwdParams& P,
-                                           const uint32_t (&off)[COLS], const int (&J)[COLS],
-                                           bool own_all, const bool (&own)[COLS], int R, int d)
+// One strip-walk iteration.  D = 0: main loop (every stage runs, quad row R
+// is stored); D < 0: prologue iteration R = R0 + D, where each stage only
+// runs once its results can feed an output row >= R0.  Q is the queue slot
+// holding input row R+5 (loaded two iterations earlier); it is refilled with
+// row R+7.
+template <int COLS, int BETA, int IO, int D>
+__device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[COLS], const StripCtx& cx,
+                                           const FwdParams& P, const StripLanes<COLS>& L, int R)
 {
-    const bool do_dd = FULL || d >= -7;
-    const bool do_sx = FULL || d >= -6;
-    const bool do_x = FULL || d >= -4;
-    const bool do_p2dd = FULL || d >= -2;
-    const bool do_p2 = FULL || d >= -1;
+    constexpr bool FULL = D == 0;
+    constexpr bool do_dd = FULL || D >= -7;
+    constexpr bool do_sx = FULL || D >= -6;
+    constexpr bool do_x = FULL || D >= -4;
+    constexpr bool do_p2dd = FULL || D >= -2;
+    constexpr bool do_p2 = FULL || D >= -1;
     const float eh = P.eps_hat, w = P.w;
 
     float V5[COLS];
 #pragma unroll
-    for (int c = 0; c < COLS; ++c) {
-        V5[c] = s.Q0[c];
-        s.Q0[c] = s.Q1[c];
-    }
-    load_row<COLS>(cx, off, R + 7, s.Q1);
+    for (int c = 0; c < COLS; ++c) V5[c] = raw_value<IO>(cx, Q[c]);
+    load_row_raw<COLS, IO>(cx, L.src_off, R + 7, Q);
 
     // ---- dd: diagonal second differences centred at (R+4, J) ----
     float dd1_4[COLS] = {}, dd2_4[COLS] = {}, dd1s_4[COLS] = {}, dd2s_4[COLS] = {};
-    if (do_dd) {
+    if constexpr (do_dd) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             dd1_4[c] = d2(lft(s.V3, c), s.V4[c], rgt(V5, c));  // (R+3,J-1) (R+4,J) (R+5,J+1)
@@ -304,7 +386,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
     // (dd centred at (R+3,J)).  Anti-diagonal line through V(R+3,J+1), V(R+4,J):
     // k1 steps (-1,+1) (dd centred at (R+3,J+1)), k3 steps (+1,-1) (dd at (R+4,J)).
     float SX3[4][COLS] = {}, PX3[4][COLS] = {};
-    if (do_sx) {
+    if constexpr (do_sx) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             const float a1 = s.V3[c], b1 = rgt(s.V4, c);
@@ -320,7 +402,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
 
     // ---- x: D over the four same-direction neighbours (I+-1, J), (I, J+-1); blend X(R+2, J) ----
     float X2[COLS] = {};
-    if (do_x) {
+    if constexpr (do_x) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             float t[4];
@@ -335,7 +417,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
 
     // ---- vertical second differences centred at row R+1 ----
     float ddXv1[COLS] = {}, ddr1[COLS] = {};
-    if (do_p2dd) {
+    if constexpr (do_p2dd) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             ddXv1[c] = d2(s.X0[c], s.X1[c], X2[c]);
@@ -346,7 +428,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
     // ---- p2: + points.  Directions k0 (+1,0) down, k1 (0,+1) right, k2 up, k3 left ----
     float SB1[4][COLS] = {}, PB1[4][COLS] = {}, hB1[4][COLS] = {};
     float SA0[4][COLS] = {}, PA0[4][COLS] = {}, hA0[4][COLS] = {};
-    if (do_p2) {
+    if constexpr (do_p2) {
         float v1r[COLS], ddc[COLS], x0l[COLS], ddXh[COLS];
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
@@ -391,7 +473,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
     }
 
     // ---- blend A(R, .), B(R, .) and store quad row R ----
-    if (FULL) {
+    if constexpr (FULL) {
         float Aq[COLS], Bq[COLS];
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
@@ -405,7 +487,8 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
             Bq[c] = blend4<BETA>(tb[0], tb[1], tb[2], tb[3], s.PB0[0][c], s.PB0[1][c], s.PB0[2][c],
                                  s.PB0[3][c], P.beta);
         }
-        store_quads<COLS>(cx, R, J, own_all, own, s.V0, Bq, Aq, s.X0);
+        if constexpr (IO == kIoGeneric) store_quads<COLS>(cx, R, L.J, L.own_all, L.own, s.V0, Bq, Aq, s.X0);
+        else store_quads_fixed<COLS, IO>(cx, R, L, s.V0, Bq, Aq, s.X0);
     }
 
     // ---- slide the windows by one row ----
@@ -425,7 +508,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, const StripCtx& 
 }
 
 // Walk one strip: columns [Jbase, Jbase + 64*COLS), output rows [R0, R1).
-template <int COLS, int BETA>
+template <int COLS, int BETA, int IO>
 __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
 {
     constexpr int SPAN = kWave * COLS;
@@ -433,19 +516,24 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
     constexpr int OWN = (COLS == 1) ? SPAN - 9 : SPAN - 10;  // even for COLS = 2 (16-byte stores)
     const int lane = threadIdx.x & (kWave - 1);
     const int Jbase = strip_x * OWN - HALO_L;
-    int J[COLS];
-    bool own[COLS];
-    uint32_t off[COLS];
-    bool own_all = true;
+    StripLanes<COLS> L;
+    L.own_all = true;
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const int sidx_ = lane * COLS + c;
-        J[c] = Jbase + sidx_;
-        own[c] = (sidx_ >= HALO_L) && (sidx_ < HALO_L + OWN) && (J[c] < cx.W);
-        own_all = own_all && own[c];
-        const int jc = J[c] < 0 ? 0 : (J[c] >= cx.W ? cx.W - 1 : J[c]);
-        off[c] = (uint32_t)jc * cx.s_w_bytes;
+        L.J[c] = Jbase + sidx_;
+        L.own[c] = (sidx_ >= HALO_L) && (sidx_ < HALO_L + OWN) && (L.J[c] < cx.W);
+        L.own_all = L.own_all && L.own[c];
+        const int jc = L.J[c] < 0 ? 0 : (L.J[c] >= cx.W ? cx.W - 1 : L.J[c]);
+        L.src_off[c] = (uint32_t)jc * cx.s_w_bytes;
+        L.st_col[c] = L.own[c] ? (uint32_t)(2 * L.J[c]) * cx.d_w : kOob;
     }
+    // f32 rows: the lane's 2*COLS floats of an output row are contiguous
+    L.st_vec = L.own_all ? (uint32_t)(2 * L.J[0]) * 4u : kOob;
+    // odd width: the lane holding column W-1 also holds W, past the image
+    const bool half = COLS == 2 && L.own[0] && !L.own_all;
+    L.st_half = half ? (uint32_t)(2 * L.J[0]) * 4u : kOob;
+    L.any_half = COLS == 2 && (cx.W & 1) && cx.W - 1 >= Jbase + HALO_L && cx.W - 1 < Jbase + HALO_L + OWN;
 
     StripState<COLS> s;
 #pragma unroll
@@ -462,18 +550,36 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
         }
     }
 
-    load_row<COLS>(cx, off, R0 - 4, s.Q0);
-    load_row<COLS>(cx, off, R0 - 3, s.Q1);
+    // two queue slots used in turn, so that a row is read two iterations
+    // after its load and a slot is never copied while its load is in flight
+    raw_t<IO> QA[COLS], QB[COLS];
+    load_row_raw<COLS, IO>(cx, L.src_off, R0 - 4, QA);
+    load_row_raw<COLS, IO>(cx, L.src_off, R0 - 3, QB);
     // prologue: rows R0-9 .. R0-1 fill the pipeline (no stores)
-    for (int d = -9; d < 0; ++d) strip_step<COLS, BETA, false>(s, cx, P, off, J, own_all, own, R0 + d, d);
+    strip_step<COLS, BETA, IO, -9>(s, QA, cx, P, L, R0 - 9);
+    strip_step<COLS, BETA, IO, -8>(s, QB, cx, P, L, R0 - 8);
+    strip_step<COLS, BETA, IO, -7>(s, QA, cx, P, L, R0 - 7);
+    strip_step<COLS, BETA, IO, -6>(s, QB, cx, P, L, R0 - 6);
+    strip_step<COLS, BETA, IO, -5>(s, QA, cx, P, L, R0 - 5);
+    strip_step<COLS, BETA, IO, -4>(s, QB, cx, P, L, R0 - 4);
+    strip_step<COLS, BETA, IO, -3>(s, QA, cx, P, L, R0 - 3);
+    strip_step<COLS, BETA, IO, -2>(s, QB, cx, P, L, R0 - 2);
+    strip_step<COLS, BETA, IO, -1>(s, QA, cx, P, L, R0 - 1);
     // main walk, two rows per trip so that values carried one row are renamed
-    // rather than copied
+    // rather than copied.  The first trip is peeled: the loop is then entered
+    // only after the memory operations of a whole trip, as on every later
+    // trip, so the compiler's wait counts for the queued loads are exact
+    // rather than those of the store-free prologue.
     int R = R0;
-    for (; R + 1 < R1; R += 2) {
-        strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R, 0);
-        strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R + 1, 0);
+    if (R + 1 < R1) {
+        strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
+        strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
+        for (R += 2; R + 1 < R1; R += 2) {
+            strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
+            strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
+        }
     }
-    if (R < R1) strip_step<COLS, BETA, true>(s, cx, P, off, J, own_all, own, R, 0);
+    if (R < R1) strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
 }
 
 }  // namespace wz
