@@ -144,10 +144,11 @@ def test_launch_configs_bit_identical(gpu):
 
 
 def test_full_size_1080p_sampled(gpu):
-    # 1920 x 1080 RGB uint8 scene, zoomed to 3840 x 2160 in the benchmark's
-    # launch configuration; sampled windows (including all four corners and
-    # edges) checked against the oracle computed on windows of the input.
-    _set(gpu, (64, 2))
+    # 1920 x 1080 RGB uint8 scene (and its planar float32 /255 version),
+    # zoomed to 3840 x 2160 in the benchmark's launch configuration (the
+    # automatic one); sampled windows (including all four corners and edges)
+    # checked against the oracle computed on windows of the input.
+    _set(gpu, (0, 0))
     img = scene_rgb(1080, 1920, seed=0)
     x = torch.tensor(img, device="cuda").permute(2, 0, 1)
     y8 = gpu.zoom2x(x).permute(1, 2, 0).cpu().numpy()
