@@ -216,23 +216,36 @@ def main():
         imgs.append(b[r0:r0 + h, c0:c0 + w])
     xs = [torch.tensor(np.ascontiguousarray(im), device=dev).permute(2, 0, 1) for im in imgs]
     ys = [torch.empty((2 * h, 2 * w, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1) for (h, w) in shapes]
+    # the persistent plan takes the autotuned strip shape (plans capture the
+    # launch configuration when made); the per-image loop runs the plain
+    # kernel in its automatic configuration
+    from paper_2312_00229_amd.autotune import tune_batched
+
+    b_rows, b_cols, _ = tune_batched(xs, ys, reps=3, use_cache=False)
     plan = wz.BatchedZoom(xs, ys)
+    wz.set_launch_config(0, 0)
     bsteps = max(3, args.steps // 20)
     ms_b = timed(plan.run, bsteps, 2, torch)
+    ys_loop = [torch.empty_like(t) for t in ys]
 
     def loop():
-        for a, b in zip(xs, ys):
+        for a, b in zip(xs, ys_loop):
             wz.zoom2x_(a, b)
 
     ms_l = timed(loop, bsteps, 2, torch)
+    identical = all(torch.equal(a, b) for a, b in zip(ys, ys_loop))
+    del ys_loop
     bpx = sum(4 * h * w for h, w in shapes)
     extras["batched_512_u8"] = {
         "ms_persistent": round(ms_b, 4), "ms_launch_loop": round(ms_l, 4),
         "Mpix_per_s_persistent": round(bpx / (ms_b * 1e-3) / 1e6, 1),
         "Mpix_per_s_launch_loop": round(bpx / (ms_l * 1e-3) / 1e6, 1),
+        "tuned_launch": {"rows_per_strip": b_rows, "cols_per_lane": b_cols},
+        "outputs_identical_to_loop": identical,
         "content": "crops of eight 1024x1024 polygon scenes, sizes U{32..1024}^2 (seed 2)",
     }
-    log("batched: persistent %.3f ms, loop %.3f ms" % (ms_b, ms_l))
+    log("batched: persistent %.3f ms (rows %d, cols %d), loop %.3f ms, identical %s"
+        % (ms_b, b_rows, b_cols, ms_l, identical))
 
     # ---------------- cascade: 256^2 pixel art, 3 doublings, HIP graph ----------------
     pa = pixel_art(256, 256, seed=1)

@@ -8,21 +8,31 @@ its registers.  Every configuration computes every quad with the same
 arithmetic, so outputs are bit-identical across configurations; the tuner
 checks that too (a cheap guard against a broken configuration).
 
+`tune_batched` does the same for a batched plan (the persistent kernel over a
+work queue): plans capture the configuration when they are made, so it builds
+one plan per candidate, checks that all outputs stay bit-identical and leaves
+the fastest configuration applied for the plans made afterwards.
+
 Results are cached in a JSON file (env WENO_TUNE_CACHE, default
 ~/.cache/weno_zoom_tune.json) keyed by device name, dtypes, channel count and
-a size class of the image.
+a size class of the image (of the batch's total size for batched plans).
+Before timing, the GPU is kept busy for a moment: its clock ramps up over the
+first tens of milliseconds of load, which would otherwise penalise the
+configurations measured first.
 """
 from __future__ import annotations
 
 import json
 import math
 import os
+import time
 
 import torch
 
-from . import get_launch_config, set_launch_config, zoom2x_
+from . import BatchedZoom, get_launch_config, set_launch_config, zoom2x_
 
 ROWS = (8, 12, 16, 20, 24, 27, 32, 40, 48, 64, 96)
+ROWS_BATCHED = (16, 24, 32, 48, 64, 96)
 COLS = (1, 2)
 
 
@@ -35,6 +45,36 @@ def _key(x: torch.Tensor, out: torch.Tensor) -> str:
     planes = int(x.numel() // (h * w))
     cls = "%dx%d" % (2 ** max(0, round(math.log2(max(h, 1)))), 2 ** max(0, round(math.log2(max(w, 1)))))
     return "%s|%s->%s|p%d|%s" % (torch.cuda.get_device_name(x.device), x.dtype, out.dtype, planes, cls)
+
+
+def _warm(fn, seconds: float = 0.1):
+    """Keep the GPU busy with fn() for about `seconds` (clock ramp-up)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def _load_cache(use_cache: bool):
+    path = _cache_path()
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as fh:
+                return json.load(fh)
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def _store_cache(cache):
+    path = _cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1)
+    os.replace(tmp, path)
 
 
 def _time(fn, reps: int) -> float:
@@ -55,14 +95,7 @@ def tune(x: torch.Tensor, out: torch.Tensor, reps: int = 30, use_cache: bool = T
     """Pick and apply the fastest (rows_per_strip, cols_per_lane) for zooming x
     into out.  Returns (rows, cols, {config: ms})."""
     key = _key(x, out)
-    path = _cache_path()
-    cache = {}
-    if use_cache and os.path.exists(path):
-        try:
-            with open(path) as fh:
-                cache = json.load(fh)
-        except (OSError, ValueError):
-            cache = {}
+    cache = _load_cache(use_cache)
     if use_cache and key in cache:
         rows, cols = cache[key]["best"]
         set_launch_config(rows, cols)
@@ -70,6 +103,7 @@ def tune(x: torch.Tensor, out: torch.Tensor, reps: int = 30, use_cache: bool = T
     prev = get_launch_config()
     times = {}
     ref = None
+    _warm(lambda: zoom2x_(x, out))
     for cols in COLS:
         for rows in ROWS:
             set_launch_config(rows, cols)
@@ -88,9 +122,50 @@ def tune(x: torch.Tensor, out: torch.Tensor, reps: int = 30, use_cache: bool = T
     set_launch_config(rows, cols)
     if use_cache:
         cache[key] = {"best": [rows, cols], "times": times}
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        tmp = path + ".tmp%d" % os.getpid()
-        with open(tmp, "w") as fh:
-            json.dump(cache, fh, indent=1)
-        os.replace(tmp, path)
+        _store_cache(cache)
+    return rows, cols, times
+
+
+def _batched_key(xs, outs) -> str:
+    px = sum(int(x.numel()) for x in xs)
+    return "batched|%s|%s->%s|n%d|px2^%d" % (torch.cuda.get_device_name(xs[0].device), xs[0].dtype, outs[0].dtype,
+                                             len(xs), round(math.log2(max(px, 1))))
+
+
+def tune_batched(xs, outs, params=None, reps: int = 5, use_cache: bool = True, verbose: bool = False):
+    """Pick and apply the fastest (rows_per_strip, cols_per_lane) for a batched
+    plan zooming xs into outs; plans made afterwards capture it.  Returns
+    (rows, cols, {config: ms})."""
+    key = _batched_key(xs, outs)
+    cache = _load_cache(use_cache)
+    if use_cache and key in cache:
+        rows, cols = cache[key]["best"]
+        set_launch_config(rows, cols)
+        return rows, cols, cache[key].get("times", {})
+    prev = get_launch_config()
+    times = {}
+    ref = None
+    for cols in COLS:
+        for rows in ROWS_BATCHED:
+            set_launch_config(rows, cols)
+            plan = BatchedZoom(xs, outs, params)
+            if ref is None:
+                _warm(plan.run)
+            plan.run()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = [o.clone() for o in outs]
+            elif not all(torch.equal(o, r) for o, r in zip(outs, ref)):
+                set_launch_config(*prev)
+                raise RuntimeError("launch configuration (%d, %d) changed the result" % (rows, cols))
+            times["%d,%d" % (rows, cols)] = _time(plan.run, reps)
+            if verbose:
+                print("batched rows %4d cols %d: %.4f ms" % (rows, cols, times["%d,%d" % (rows, cols)]), flush=True)
+    del ref
+    best = min(times, key=times.get)
+    rows, cols = (int(t) for t in best.split(","))
+    set_launch_config(rows, cols)
+    if use_cache:
+        cache[key] = {"best": [rows, cols], "times": times}
+        _store_cache(cache)
     return rows, cols, times
