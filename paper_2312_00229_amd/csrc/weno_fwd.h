@@ -15,7 +15,7 @@
 // strip walk starts 9 rows above its first output row to fill the pipeline.
 //
 // Per iteration R (output quad row R) the stages are, in dependency order:
-//   load   V(R+5)
+//   load   consume V(R+5) from the two-row prefetch queue, request V(R+7)
 //   dd     diagonal second differences at input row R+4
 //   sx     phase-1 candidates p and indicators SI of x points at row R+3
 //   x      D = SI + w * (4 neighbours) and the blend for x points at row R+2
