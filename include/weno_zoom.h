@@ -193,9 +193,11 @@ int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, co
  * call; the Python autotuner sets it).
  *   rows_per_strip: output rows one wave walks down, in [4, 4096]
  *   cols_per_lane:  1 or 2 columns of quads per lane
- * (0, 0) selects the automatic choice (the default): two columns per lane for
- * images at least 256 wide, and a strip height (8..64 rows) that gives about
- * two waves per SIMD of the device.  The configuration changes speed only: every
+ * (0, 0) selects the automatic choice (the default): the columns per lane and
+ * strip height that minimise a cost model of the launch (waves per SIMD x
+ * iterations per wave x measured time per iteration); e.g. two columns and
+ * 27-row strips for a 1920x1080 RGB frame, one column and 4-row strips for a
+ * 256x256 one.  The configuration changes speed only: every
  * configuration produces bit-identical outputs.  Batched plans capture the
  * configuration when they are made (automatic: 32 rows, 2 columns).
  * weno_get_launch_config reports (0, 0) in automatic mode.  An explicit

@@ -110,9 +110,13 @@ __global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable
         const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
         const int R0 = sy * rows_per_strip;
         const int R1 = min(R0 + rows_per_strip, jb.H);
-        if (jb.io == kIoF32) zoom_strip<COLS, BETA, kIoF32>(cx, P, sx, R0, R1);
-        else if (jb.io == kIoU8) zoom_strip<COLS, BETA, kIoU8>(cx, P, sx, R0, R1);
-        else zoom_strip<COLS, BETA, kIoGeneric>(cx, P, sx, R0, R1);
+        switch (jb.io) {
+        case kIoF32: zoom_strip<COLS, BETA, kIoF32>(cx, P, sx, R0, R1); break;
+        case kIoU8: zoom_strip<COLS, BETA, kIoU8>(cx, P, sx, R0, R1); break;
+        case kIoU8F32: zoom_strip<COLS, BETA, kIoU8F32>(cx, P, sx, R0, R1); break;
+        case kIoF32U8: zoom_strip<COLS, BETA, kIoF32U8>(cx, P, sx, R0, R1); break;
+        default: zoom_strip<COLS, BETA, kIoGeneric>(cx, P, sx, R0, R1); break;
+        }
     }
 }
 
@@ -293,9 +297,13 @@ FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols,
         vec = a16 ? 2 : (a8 ? 1 : 0);
     }
     jb.vec = vec;
-    if (!jb.in_u8 && !jb.out_u8 && (cols == 2 ? vec == 2 : vec >= 1)) jb.io = kIoF32;
-    else if (jb.in_u8 && jb.out_u8) jb.io = kIoU8;
-    else jb.io = kIoGeneric;
+    // fixed-layout I/O modes where the layout allows (float rows need vector
+    // stores: contiguous, aligned destination columns)
+    const bool vec_rows = cols == 2 ? vec == 2 : vec >= 1;
+    if (jb.in_u8 && jb.out_u8) jb.io = kIoU8;
+    else if (!jb.in_u8 && jb.out_u8) jb.io = kIoF32U8;
+    else if (!vec_rows) jb.io = kIoGeneric;
+    else jb.io = jb.in_u8 ? kIoU8F32 : kIoF32;
     jb.src_extent = (uint32_t)wz_plane_extent(src);
     jb.dst_extent = (uint32_t)wz_plane_extent(dst);
     return jb;
@@ -335,9 +343,13 @@ static hipError_t launch_fwd_io(const FwdJob& jb, const FwdParams& P, int beta_m
 template <int COLS>
 static hipError_t launch_fwd_cols(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
 {
-    if (jb.io == kIoF32) return launch_fwd_io<COLS, kIoF32>(jb, P, beta_mode, rows, st);
-    if (jb.io == kIoU8) return launch_fwd_io<COLS, kIoU8>(jb, P, beta_mode, rows, st);
-    return launch_fwd_io<COLS, kIoGeneric>(jb, P, beta_mode, rows, st);
+    switch (jb.io) {
+    case kIoF32: return launch_fwd_io<COLS, kIoF32>(jb, P, beta_mode, rows, st);
+    case kIoU8: return launch_fwd_io<COLS, kIoU8>(jb, P, beta_mode, rows, st);
+    case kIoU8F32: return launch_fwd_io<COLS, kIoU8F32>(jb, P, beta_mode, rows, st);
+    case kIoF32U8: return launch_fwd_io<COLS, kIoF32U8>(jb, P, beta_mode, rows, st);
+    default: return launch_fwd_io<COLS, kIoGeneric>(jb, P, beta_mode, rows, st);
+    }
 }
 
 // SIMDs of the current device (4 per compute unit), cached per device
@@ -356,23 +368,53 @@ static int device_simds()
     return v;
 }
 
-// Automatic launch configuration: two quad columns per lane for images at
-// least 256 wide; the strip height splits every strip column into bands so
-// that the launch has about two equal waves per SIMD (waves are independent
-// and equally long, so equal counts per SIMD finish together), but never
-// below 8 rows (the 9-row pipeline fill) or above 64.
+// Automatic launch configuration from a cost model of the strip walk.  A
+// launch takes about
+//   m x (rows + 8) x R(cols, m)
+// where m = ceil(waves / SIMDs) is the number of waves a SIMD runs (they are
+// independent and equally long), rows + 8 the iterations of one wave (the
+// 9-row pipeline fill costs nearly as much as output rows when latency-bound)
+// and R(cols, m) the time of one iteration of one of m waves sharing a SIMD,
+// measured on MI355X (one or two quad columns per lane; a lone wave is
+// latency-bound, several share the VALU).  Candidates are, for each column
+// count and each m = 1..8, the tallest strips that give at most m waves per
+// SIMD; the cheapest wins (fewer columns per lane only when strictly cheaper).
+// On planes of 64x64 .. 4096x4096 this picks within ~10 % of the best of a
+// sweep; at 1080p RGB it gives two columns and 27-row strips.
+static double iteration_cost(int cols, int64_t m)
+{
+    // microseconds per iteration, fitted to kernel traces of 64x64 .. 4096x4096
+    // planes at the launch shapes that fill 1..9 waves per SIMD
+    static const double one[4] = {0.47, 0.34, 0.325, 0.295};
+    static const double two[4] = {0.71, 0.58, 0.58, 0.55};
+    return (cols == 1 ? one : two)[m < 4 ? m - 1 : 3];
+}
+
 void wz_auto_config(int64_t planes, int H, int W, int* rows, int* cols)
 {
-    const int c = W >= 256 ? 2 : 1;
-    const int own = c == 1 ? kWave - 9 : 2 * kWave - 10;
-    const int64_t columns = planes * ((W + own - 1) / own);
-    const int64_t target = 2 * (int64_t)device_simds();
-    int64_t bands = target / columns;  // never more waves than two per SIMD: no tail round
-    if (bands < 1) bands = 1;
-    int r = (int)((H + bands - 1) / bands);
-    r = r < 8 ? 8 : (r > 64 ? 64 : r);
-    *rows = r;
-    *cols = c;
+    const int64_t simds = device_simds();
+    double best = 0.0;
+    int best_rows = 8, best_cols = 2;
+    for (int c = 2; c >= 1; --c) {
+        const int own = c == 1 ? kWave - 9 : 2 * kWave - 10;
+        const int64_t columns = planes * ((W + own - 1) / own);
+        for (int64_t m = 1; m <= 8; ++m) {
+            int64_t bands = m * simds / columns;
+            if (bands < 1) bands = 1;
+            int r = (int)((H + bands - 1) / bands);
+            r = r < 4 ? 4 : (r > 4096 ? 4096 : r);
+            const int64_t waves = columns * ((H + r - 1) / r);
+            const int64_t mm = (waves + simds - 1) / simds;
+            const double cost = (double)mm * (r + 8) * iteration_cost(c, mm);
+            if (best == 0.0 || cost < best) {
+                best = cost;
+                best_rows = r;
+                best_cols = c;
+            }
+        }
+    }
+    *rows = best_rows;
+    *cols = best_cols;
 }
 
 void wz_config_for(const weno_tensor_t* src, int* rows, int* cols)

@@ -50,6 +50,12 @@ constexpr int kBetaGeneral = -1;
 constexpr int kIoGeneric = 0;  // any dtype pair, strides and output scale (runtime flags)
 constexpr int kIoF32 = 1;      // f32 -> f32, destination columns contiguous and vector-aligned
 constexpr int kIoU8 = 2;       // u8 -> u8, any strides
+constexpr int kIoU8F32 = 3;    // u8 -> f32 (x 1/255), destination as for kIoF32
+constexpr int kIoF32U8 = 4;    // f32 -> u8 (x 255), any strides
+constexpr bool io_in_u8(int io) { return io == kIoU8 || io == kIoU8F32; }
+constexpr bool io_out_u8(int io) { return io == kIoU8 || io == kIoF32U8; }
+// the output scale is 1 when both ends have the same dtype
+constexpr bool io_scaled(int io) { return io == kIoU8F32 || io == kIoF32U8; }
 
 // A buffer offset past every plane extent (planes span less than 2^31 bytes):
 // loads through it return 0 and stores through it are dropped by the buffer
@@ -214,14 +220,14 @@ struct StripCtx {
 // queue word of an I/O mode: the u8 mode keeps the loaded byte as a byte, so
 // that its widening folds into the conversion at the consuming iteration
 template <int IO>
-using raw_t = typename std::conditional<IO == kIoU8, uint8_t, uint32_t>::type;
+using raw_t = typename std::conditional<io_in_u8(IO), uint8_t, uint32_t>::type;
 
 template <int COLS, int IO>
 __device__ __forceinline__ void load_row_raw(const StripCtx& cx, const uint32_t (&off)[COLS], int r, raw_t<IO> (&q)[COLS])
 {
     const int rc = r < 0 ? 0 : (r >= cx.H ? cx.H - 1 : r);
     const uint32_t soff = (uint32_t)rc * cx.s_h;
-    const bool u8 = IO == kIoU8 || (IO == kIoGeneric && cx.in_u8);
+    const bool u8 = io_in_u8(IO) || (IO == kIoGeneric && cx.in_u8);
     if (u8) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) q[c] = __builtin_amdgcn_raw_buffer_load_b8(cx.src, (int)off[c], (int)soff, 0);
@@ -234,8 +240,8 @@ __device__ __forceinline__ void load_row_raw(const StripCtx& cx, const uint32_t 
 template <int IO>
 __device__ __forceinline__ float raw_value(const StripCtx& cx, raw_t<IO> q)
 {
-    if constexpr (IO == kIoU8) return (float)q;
-    else if constexpr (IO == kIoF32) {
+    if constexpr (io_in_u8(IO)) return (float)q;
+    else if constexpr (IO != kIoGeneric) {
         // an explicit copy into a register of its own: the slot's register is
         // then free for the row loaded next, so it stays the loop-carried
         // register and is not copied (waiting for that load) at the back edge
@@ -254,7 +260,8 @@ __device__ __forceinline__ float raw_value(const StripCtx& cx, raw_t<IO> q)
 __device__ __forceinline__ uint32_t quant_u8(float u) { return __builtin_amdgcn_cvt_pk_u8_f32(u, 0u, 0u); }
 
 // store the 2x2 quads of row R for this lane's columns: fixed layouts,
-// branch-free (lanes that own nothing store through kOob)
+// branch-free (lanes that own nothing store through kOob).  Mixed dtypes
+// scale by out_scale (255 or 1/255), as the runtime-flag path does.
 template <int COLS, int IO>
 __device__ __forceinline__ void store_quads_fixed(const StripCtx& cx, int R, const StripLanes<COLS>& L,
                                                   const float (&o00)[COLS], const float (&o01)[COLS],
@@ -262,26 +269,36 @@ __device__ __forceinline__ void store_quads_fixed(const StripCtx& cx, int R, con
 {
     const uint32_t r0 = (uint32_t)(2 * R) * cx.d_h;
     const uint32_t r1 = r0 + cx.d_h;
-    if constexpr (IO == kIoF32) {
+    float a[COLS], b[COLS], c[COLS], d[COLS];
+#pragma unroll
+    for (int k = 0; k < COLS; ++k) {
+        if constexpr (io_scaled(IO)) {
+            const float s = cx.out_scale;
+            a[k] = o00[k] * s; b[k] = o01[k] * s; c[k] = o10[k] * s; d[k] = o11[k] * s;
+        } else {
+            a[k] = o00[k]; b[k] = o01[k]; c[k] = o10[k]; d[k] = o11[k];
+        }
+    }
+    if constexpr (!io_out_u8(IO)) {
         if constexpr (COLS == 2) {
-            buf_st_f32x4(o00[0], o01[0], o00[1], o01[1], cx.dst, L.st_vec, r0);
-            buf_st_f32x4(o10[0], o11[0], o10[1], o11[1], cx.dst, L.st_vec, r1);
+            buf_st_f32x4(a[0], b[0], a[1], b[1], cx.dst, L.st_vec, r0);
+            buf_st_f32x4(c[0], d[0], c[1], d[1], cx.dst, L.st_vec, r1);
             if (L.any_half) {
-                buf_st_f32x2(o00[0], o01[0], cx.dst, L.st_half, r0);
-                buf_st_f32x2(o10[0], o11[0], cx.dst, L.st_half, r1);
+                buf_st_f32x2(a[0], b[0], cx.dst, L.st_half, r0);
+                buf_st_f32x2(c[0], d[0], cx.dst, L.st_half, r1);
             }
         } else {
-            buf_st_f32x2(o00[0], o01[0], cx.dst, L.st_vec, r0);
-            buf_st_f32x2(o10[0], o11[0], cx.dst, L.st_vec, r1);
+            buf_st_f32x2(a[0], b[0], cx.dst, L.st_vec, r0);
+            buf_st_f32x2(c[0], d[0], cx.dst, L.st_vec, r1);
         }
-    } else {  // kIoU8: one byte per output, value scale unchanged
+    } else {  // one byte per output
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) {
-            const uint32_t off0 = L.st_col[c];
-            buf_st_u8(quant_u8(o00[c]), cx.dst, off0, r0);
-            buf_st_u8(quant_u8(o01[c]), cx.dst, off0 + cx.d_w, r0);
-            buf_st_u8(quant_u8(o10[c]), cx.dst, off0, r1);
-            buf_st_u8(quant_u8(o11[c]), cx.dst, off0 + cx.d_w, r1);
+        for (int k = 0; k < COLS; ++k) {
+            const uint32_t off0 = L.st_col[k];
+            buf_st_u8(quant_u8(a[k]), cx.dst, off0, r0);
+            buf_st_u8(quant_u8(b[k]), cx.dst, off0 + cx.d_w, r0);
+            buf_st_u8(quant_u8(c[k]), cx.dst, off0, r1);
+            buf_st_u8(quant_u8(d[k]), cx.dst, off0 + cx.d_w, r1);
         }
     }
 }
