@@ -372,9 +372,10 @@ static int device_simds()
 // launch takes about
 //   m x (rows + 8) x R(cols, m)
 // where m = ceil(waves / SIMDs) is the number of waves a SIMD runs (they are
-// independent and equally long), rows + 8 the iterations of one wave (the
-// 9-row pipeline fill costs nearly as much as output rows when latency-bound)
-// and R(cols, m) the time of one iteration of one of m waves sharing a SIMD,
+// independent and equally long), rows + 8 the iterations of one wave plus the
+// fixed cost of starting it (its launch and the 9-row pipeline fill, about 8
+// iterations' worth in the fit) and R(cols, m) the time of one iteration of
+// one of m waves sharing a SIMD,
 // measured on MI355X (one or two quad columns per lane; a lone wave is
 // latency-bound, several share the VALU).  Candidates are, for each column
 // count and each m = 1..8, the tallest strips that give at most m waves per

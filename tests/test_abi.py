@@ -58,6 +58,28 @@ def test_null_and_size_errors():
     assert call_zoom(src, _t(ptr=0x100000, c=2, h=8, w=10), p) == _lib.WENO_EINVAL
 
 
+def test_plane_size_limits():
+    # buffer offsets are 32-bit: every plane must span less than 2^31 bytes
+    p = _p()
+    big = 23171                     # a float plane of big^2 elements spans > 2^31 bytes
+    assert call_zoom(_t(h=big, w=big), _t(ptr=1 << 40, h=2 * big, w=2 * big), p) == _lib.WENO_EINVAL
+    # source fine (1 GiB), destination over the limit (4 GiB)
+    assert call_zoom(_t(h=16384, w=16384), _t(ptr=1 << 40, h=32768, w=32768), p) == _lib.WENO_EINVAL
+    # uint8 destination just over the limit: 2*23171 squared bytes
+    u8 = _lib.WENO_U8
+    assert call_zoom(_t(dtype=u8, h=big, w=big), _t(ptr=1 << 40, dtype=u8, h=2 * big, w=2 * big), p) == _lib.WENO_EINVAL
+    # at most 65535 planes (one grid dimension)
+    assert call_zoom(_t(n=65536, h=2, w=2), _t(ptr=1 << 40, n=65536, h=4, w=4), p) == _lib.WENO_EINVAL
+    assert call_zoom(_t(n=256, c=256, h=2, w=2), _t(ptr=1 << 40, n=256, c=256, h=4, w=4), p) == _lib.WENO_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
+
+
 def test_dtype_error():
     assert call_zoom(_t(dtype=7), _t(ptr=0x100000, h=8, w=10), _p()) == _lib.WENO_EDTYPE
 
