@@ -30,7 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# FP32 VALU peak without packed math (the build disables packed FP32):
+# FP32 VALU peak without packed math (the library is compiled with packed FP32 off):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6432
 # algorithmic FP32 operations per output quad per channel (FMA = 2, rcp = 1):
@@ -121,7 +121,7 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 

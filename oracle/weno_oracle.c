@@ -14,7 +14,7 @@
  * index i runs along the first array axis (image rows), j along the second.
  *
  * Readings of passages the paper leaves open (each one is a switch or a
- * documented default; see the design notes of the repository):
+ * documented default):
  *   - boundary: input samples outside the image are clamped to the edge;
  *     function tests instead pass an input that already extends >= 5 samples
  *     beyond the domain and crop the result;

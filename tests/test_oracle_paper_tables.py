@@ -1,6 +1,6 @@
 """Reproduction of the paper's printed numbers (Section 4, Tables 1 and 2).
 
-Readings (recorded in the design notes):
+Readings of the paper used here:
   * the tables' h is the spacing of the zoomed grid; the input spacing is 2h,
     nodes -1 + 2hk, n = 1/h + 1 per side, output (2n-1)^2 points on [-1,1]^2;
   * samples outside [-1,1]^2 are f itself (ghost samples): row 1 of Table 1,
