@@ -200,15 +200,25 @@ int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, co
  * 256x256 one.  The configuration changes speed only: every
  * configuration produces bit-identical outputs.  Batched plans capture the
  * configuration when they are made (automatic: 32 rows, 2 columns).
- * weno_get_launch_config reports (0, 0) in automatic mode.  An explicit
- * rows_per_strip also sets the strip height of the adjoint kernel (which
- * always uses one column per lane; automatic: the height that minimises the
- * rounds of resident waves times the rows each wave walks), whose results are
- * also bit-identical across strip heights.
+ * weno_get_launch_config reports (0, 0) in automatic mode.
  * Returns WENO_EINVAL for values outside these sets.
  */
 int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane);
 void weno_get_launch_config(int32_t* rows_per_strip, int32_t* cols_per_lane);
+
+/*
+ * Strip height of the adjoint kernel (weno_zoom2x_backward; process-global,
+ * read at each call), independent of the forward's configuration.  The
+ * adjoint always runs one column per lane.
+ *   rows_per_strip: input rows one wave walks, in [4, 4096]; 0 selects the
+ *                   automatic choice (the default): the height that minimises
+ *                   the rounds of resident waves times the rows each wave
+ *                   walks.
+ * Gradients are bit-identical across strip heights.  Returns WENO_EINVAL for
+ * values outside these sets.
+ */
+int weno_set_backward_launch_config(int32_t rows_per_strip);
+void weno_get_backward_launch_config(int32_t* rows_per_strip);
 
 /* Text for a status code; for WENO_EHIP the last HIP error seen by this
  * thread.  The pointer stays valid until the next call on the same thread. */

@@ -33,6 +33,8 @@ __all__ = [
     "WenoZoom2x",
     "set_launch_config",
     "get_launch_config",
+    "set_backward_launch_config",
+    "get_backward_launch_config",
     "WenoError",
 ]
 
@@ -249,3 +251,14 @@ def get_launch_config():
     r, c = ctypes.c_int32(), ctypes.c_int32()
     _lib.lib().weno_get_launch_config(ctypes.byref(r), ctypes.byref(c))
     return int(r.value), int(c.value)
+
+
+def set_backward_launch_config(rows_per_strip: int):
+    """Strip height of the adjoint kernel (0 = automatic)."""
+    _lib.check(_lib.lib().weno_set_backward_launch_config(int(rows_per_strip)), "weno_set_backward_launch_config")
+
+
+def get_backward_launch_config() -> int:
+    r = ctypes.c_int32()
+    _lib.lib().weno_get_backward_launch_config(ctypes.byref(r))
+    return int(r.value)

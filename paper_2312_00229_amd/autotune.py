@@ -8,7 +8,10 @@ its registers.  Every configuration computes every quad with the same
 arithmetic, so outputs are bit-identical across configurations; the tuner
 checks that too (a cheap guard against a broken configuration).
 
-`tune_batched` does the same for a batched plan (the persistent kernel over a
+`tune_backward` picks the adjoint kernel's strip height (its own setting;
+it always runs one column per lane), checking that the gradient stays
+bit-identical.  `tune_batched` does the same for a
+batched plan (the persistent kernel over a
 work queue): plans capture the configuration when they are made, so it builds
 one plan per candidate, checks that all outputs stay bit-identical and leaves
 the fastest configuration applied for the plans made afterwards.
@@ -29,10 +32,12 @@ import time
 
 import torch
 
-from . import BatchedZoom, get_launch_config, set_launch_config, zoom2x_
+from . import (BatchedZoom, get_backward_launch_config, get_launch_config, set_backward_launch_config,
+               set_launch_config, zoom2x_, zoom2x_backward)
 
 ROWS = (8, 12, 16, 20, 24, 27, 32, 40, 48, 64, 96)
 ROWS_BATCHED = (16, 24, 32, 48, 64, 96)
+ROWS_BACKWARD = (16, 24, 32, 48, 64, 96, 128, 171, 256)
 COLS = (1, 2)
 
 
@@ -169,3 +174,42 @@ def tune_batched(xs, outs, params=None, reps: int = 5, use_cache: bool = True, v
         cache[key] = {"best": [rows, cols], "times": times}
         _store_cache(cache)
     return rows, cols, times
+
+
+def tune_backward(x, grad_y, reps: int = 5, use_cache: bool = True, verbose: bool = False):
+    """Pick and apply the fastest strip height for the adjoint of zooming x
+    (gradient grad_y of the output); the forward's configuration is left
+    alone.  Returns (rows, {rows: ms})."""
+    h, w = x.shape[-2:]
+    planes = int(x.numel() // (h * w))
+    cls = "%dx%d" % (2 ** max(0, round(math.log2(max(h, 1)))), 2 ** max(0, round(math.log2(max(w, 1)))))
+    key = "backward|%s|p%d|%s" % (torch.cuda.get_device_name(x.device), planes, cls)
+    cache = _load_cache(use_cache)
+    if use_cache and key in cache:
+        rows = cache[key]["best"]
+        set_backward_launch_config(rows)
+        return rows, cache[key].get("times", {})
+    prev = get_backward_launch_config()
+    times = {}
+    ref = None
+    for rows in ROWS_BACKWARD:
+        set_backward_launch_config(rows)
+        if ref is None:
+            _warm(lambda: zoom2x_backward(x, grad_y))
+        g = zoom2x_backward(x, grad_y)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = g
+        elif not torch.equal(g, ref):
+            set_backward_launch_config(prev)
+            raise RuntimeError("adjoint strip height %d changed the gradient" % rows)
+        times[str(rows)] = _time(lambda: zoom2x_backward(x, grad_y), reps)
+        if verbose:
+            print("backward rows %4d: %.4f ms" % (rows, times[str(rows)]), flush=True)
+    best = min(times, key=times.get)
+    rows = int(best)
+    set_backward_launch_config(rows)
+    if use_cache:
+        cache[key] = {"best": rows, "times": times}
+        _store_cache(cache)
+    return rows, times

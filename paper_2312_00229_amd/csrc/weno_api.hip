@@ -193,7 +193,6 @@ extern "C" void weno_get_launch_config(int32_t* rows_per_strip, int32_t* cols_pe
 // --------------------------------------------------------------------------
 int wz_esize(int32_t dtype) { return dtype == WENO_U8 ? 1 : (dtype == WENO_F32 ? 4 : 0); }
 
-int wz_explicit_rows() { return g_rows_per_strip.load(); }
 
 int wz_check_tensor(const weno_tensor_t* t)
 {

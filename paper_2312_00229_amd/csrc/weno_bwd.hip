@@ -94,6 +94,21 @@ int bwd_auto_rows(int H, int strips_x, int64_t planes, int64_t resident)
 
 }  // namespace
 
+// strip height of the adjoint set by weno_set_backward_launch_config (0 = automatic)
+static std::atomic<int32_t> g_bwd_rows{0};
+
+extern "C" int weno_set_backward_launch_config(int32_t rows_per_strip)
+{
+    if (rows_per_strip != 0 && (rows_per_strip < 4 || rows_per_strip > 4096)) return WENO_EINVAL;
+    g_bwd_rows.store(rows_per_strip);
+    return WENO_OK;
+}
+
+extern "C" void weno_get_backward_launch_config(int32_t* rows_per_strip)
+{
+    if (rows_per_strip) *rows_per_strip = g_bwd_rows.load();
+}
+
 FwdParams wz_fwd_params(const weno_params_t* p, int in_u8, int out_u8);
 
 extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, const weno_tensor_t* grad_x,
@@ -136,7 +151,8 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     const int strips_x = (x->w + bwd_strip_width(x->w) - 1) / bwd_strip_width(x->w);
     const int64_t planes = (int64_t)x->n * x->c;
     int rows = bwd_auto_rows(x->h, strips_x, planes, bwd_resident_blocks());
-    if (wz_explicit_rows() > 0) rows = wz_explicit_rows();
+    const int explicit_rows = g_bwd_rows.load();
+    if (explicit_rows > 0) rows = explicit_rows;
     const int strips_y = (x->h + rows - 1) / rows;
     dim3 grid((strips_x * strips_y + kWavesPerBlock - 1) / kWavesPerBlock, x->n * x->c);
     hipStream_t st = (hipStream_t)hip_stream;

@@ -59,4 +59,3 @@ bool wz_overlap(const weno_tensor_t* a, const weno_tensor_t* b);
 int64_t wz_plane_extent(const weno_tensor_t* t);
 double wz_nbw(const weno_params_t* p);
 int wz_beta_mode(float beta);
-int wz_explicit_rows();  // rows_per_strip set by weno_set_launch_config, 0 in automatic mode

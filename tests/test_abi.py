@@ -153,6 +153,19 @@ def test_launch_config_validation():
     assert L.weno_set_launch_config(8192, 1) == _lib.WENO_EINVAL
     assert L.weno_set_launch_config(0, 0) == _lib.WENO_OK
     assert L.weno_set_launch_config(r.value, c.value) == _lib.WENO_OK
+    # the adjoint's strip height is separate: 0 (automatic) or 4..4096
+    b = ctypes.c_int32(-1)
+    L.weno_get_backward_launch_config(ctypes.byref(b))
+    assert b.value == 0
+    for bad in (3, -1, 4097):
+        assert L.weno_set_backward_launch_config(bad) == _lib.WENO_EINVAL
+    assert L.weno_set_backward_launch_config(96) == _lib.WENO_OK
+    L.weno_get_backward_launch_config(ctypes.byref(b))
+    assert b.value == 96
+    r2, c2 = ctypes.c_int32(), ctypes.c_int32()
+    L.weno_get_launch_config(ctypes.byref(r2), ctypes.byref(c2))
+    assert (r2.value, c2.value) == (r.value, c.value)               # the forward setting is unaffected
+    assert L.weno_set_backward_launch_config(0) == _lib.WENO_OK
 
 
 def test_status_strings():

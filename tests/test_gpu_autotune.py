@@ -60,3 +60,25 @@ def test_tune_batched_plan(gpu, tune_cache):
             assert torch.equal(o, r)
     finally:
         gpu.set_launch_config(0, 0)
+
+
+def test_tune_backward(gpu, tune_cache):
+    from paper_2312_00229_amd import autotune
+
+    rng = np.random.default_rng(3)
+    x = torch.tensor(rng.random((2, 3, 96, 130), dtype=np.float32), device="cuda")
+    g = torch.tensor(rng.standard_normal((2, 3, 192, 260)).astype(np.float32), device="cuda")
+    try:
+        gpu.set_backward_launch_config(0)
+        gpu.set_launch_config(0, 0)
+        ref = gpu.zoom2x_backward(x, g)
+        rows, times = autotune.tune_backward(x, g, reps=2)
+        assert rows in autotune.ROWS_BACKWARD
+        assert len(times) == len(autotune.ROWS_BACKWARD)
+        assert gpu.get_backward_launch_config() == rows
+        assert gpu.get_launch_config() == (0, 0)                       # the forward is left alone
+        assert torch.equal(gpu.zoom2x_backward(x, g), ref)
+        gpu.set_backward_launch_config(0)
+        assert autotune.tune_backward(x, g, reps=2)[0] == rows        # served from the cache
+    finally:
+        gpu.set_backward_launch_config(0)

@@ -93,9 +93,14 @@ def test_backward_independent_of_strip_height(gpu):
     ref = gpu.zoom2x_backward(x, g)
     try:
         for rows in (4, 5, 8, 13, 32, 64, 149):
-            gpu.set_launch_config(rows, 1)
+            gpu.set_backward_launch_config(rows)
             assert torch.equal(gpu.zoom2x_backward(x, g), ref), rows
+        # the forward's launch configuration does not reach the adjoint
+        gpu.set_backward_launch_config(0)
+        gpu.set_launch_config(8, 1)
+        assert torch.equal(gpu.zoom2x_backward(x, g), ref)
     finally:
+        gpu.set_backward_launch_config(0)
         gpu.set_launch_config(0, 0)
 
 
