@@ -196,6 +196,37 @@ def main():
         return
 
     extras = {}
+    # ---------------- the headline launch replayed from a HIP graph ----------------
+    # (no host launch cost between kernels; the back-to-back stream launches
+    # above hide it already, which the two figures show)
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(gs):
+        wz.zoom2x_(x, y)
+    torch.cuda.current_stream().wait_stream(gs)
+    gh = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gh):
+        for _ in range(20):
+            wz.zoom2x_(x, y)
+    ms_gh = timed(gh.replay, max(5, args.steps // 20), 5, torch) / 20
+    extras["headline_graph_replay"] = {"ms": round(ms_gh, 5), "Mpix_per_s": round(out_px / (ms_gh * 1e-3) / 1e6, 1),
+                                       "launches_per_graph": 20}
+    log("headline from a graph: %.4f ms per launch" % ms_gh)
+    del gh
+
+    # ---------------- a frame whose working set exceeds the 256 MB MALL ----------------
+    H8, W8 = 4320, 7680
+    x8k = torch.tensor(to_planar_f32(scene_rgb(H8, W8, seed=3, n_polygons=40)), device=dev)
+    y8k = torch.empty((3, 2 * H8, 2 * W8), dtype=torch.float32, device=dev)
+    ms8k = timed(lambda: wz.zoom2x_(x8k, y8k), max(20, args.steps // 10), 20, torch)
+    px8k = 4 * H8 * W8
+    extras["zoom2x_rgb_f32_7680x4320"] = {
+        "ms": round(ms8k, 4), "Mpix_per_s": round(px8k / (ms8k * 1e-3) / 1e6, 1),
+        "GBps_algorithmic": round(15 * px8k / (ms8k * 1e-3) / 1e9, 1),
+        "TFLOPs_algorithmic": round(FLOPS_PER_QUAD * 3 * H8 * W8 / (ms8k * 1e-3) / 1e12, 2)}
+    log("7680x4320 RGB fp32: %.4f ms" % ms8k)
+    del x8k, y8k
+
     # ---------------- uint8 HWC variant of the same frame ----------------
     x8 = torch.tensor(img, device=dev).permute(2, 0, 1)
     y8 = torch.empty((2 * H, 2 * W, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1)
