@@ -172,27 +172,37 @@ def test_full_size_1080p_sampled(gpu):
 
 @pytest.mark.parametrize("cfg", [(8, 2), (16, 1)])
 @pytest.mark.parametrize("W", [131, 132, 1, 57])
-def test_padded_output_rows_untouched(gpu, cfg, W):
-    """Output rows inside a wider buffer (contiguous columns, padded rows):
-    every output is written and the padding past each row keeps its bytes.
-    Covers the vector-store float path (odd widths end in a half store) and
-    the byte path, whose lanes outside the image store nothing."""
+@pytest.mark.parametrize("dtypes", ["f32->f32", "u8->u8", "u8->f32", "f32->u8"])
+def test_padded_output_rows_untouched(gpu, cfg, W, dtypes):
+    """Planar outputs inside a wider buffer (contiguous columns, padded rows),
+    for every dtype pair: every output is written, matches the oracle, and the
+    padding past each row keeps its bytes.  Covers the fixed-layout kernels
+    (float rows with vector stores -- odd widths end in a half store -- and
+    byte rows, whose lanes outside the image store nothing) and, where the
+    padded float rows are not 16-byte aligned, the runtime-flag path."""
     _set(gpu, cfg)
     H, pad = 21, 6
+    src_t, dst_t = dtypes.split("->")
     V = random_plane(H, W, seed=W, kind="steps") * 0.6 + 0.4 * random_plane(H, W, seed=3, kind="uniform")
-    V32 = V.astype(np.float32)
-    ref = oracle.zoom2x(V32.astype(np.float64))
-    big = torch.full((2 * H, 2 * W + pad), -7.0, device="cuda")
+    if src_t == "u8":
+        img = (V * 255.0).round().astype(np.uint8)
+        x = torch.tensor(img, device="cuda")
+        ref = oracle.zoom2x(img.astype(np.float64) / 255.0)
+    else:
+        V32 = V.astype(np.float32)
+        x = _f32(V32)
+        ref = oracle.zoom2x(V32.astype(np.float64))
+    if dst_t == "u8":
+        big = torch.full((2 * H, 2 * W + pad), 201, dtype=torch.uint8, device="cuda")
+    else:
+        big = torch.full((2 * H, 2 * W + pad), -7.0, device="cuda")
     out = big[:, : 2 * W]
-    gpu.zoom2x_(_f32(V32), out)
-    assert np.abs(out.cpu().numpy() - ref).max() <= TOL
-    assert bool((big[:, 2 * W:] == -7.0).all())
-    # uint8 planes, same layout
-    img = (V * 255.0).round().astype(np.uint8)
-    ref8 = oracle.zoom2x(img.astype(np.float64) / 255.0)
-    big8 = torch.full((2 * H, 2 * W + pad), 201, dtype=torch.uint8, device="cuda")
-    out8 = big8[:, : 2 * W]
-    gpu.zoom2x_(torch.tensor(img, device="cuda"), out8)
-    ties, errors = u8_compare(out8.cpu().numpy(), ref8)
-    assert errors == 0
-    assert bool((big8[:, 2 * W:] == 201).all())
+    gpu.zoom2x_(x, out)
+    got = out.cpu().numpy()
+    if dst_t == "u8":
+        ties, errors = u8_compare(got, ref)
+        assert errors == 0
+        assert bool((big[:, 2 * W:] == 201).all())
+    else:
+        assert np.abs(got - ref).max() <= TOL
+        assert bool((big[:, 2 * W:] == -7.0).all())
