@@ -36,7 +36,7 @@ from . import (BatchedZoom, get_backward_launch_config, get_launch_config, set_b
                set_launch_config, zoom2x_, zoom2x_backward)
 
 ROWS = (8, 12, 16, 20, 24, 27, 32, 40, 48, 64, 96)
-ROWS_BATCHED = (16, 24, 32, 48, 64, 96)
+ROWS_BATCHED = (16, 24, 32, 48, 64, 96, 128, 192)
 ROWS_BACKWARD = (16, 24, 32, 48, 64, 96, 128, 171, 256)
 COLS = (1, 2)
 
