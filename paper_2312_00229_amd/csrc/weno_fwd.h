@@ -578,18 +578,48 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
     strip_step<COLS, BETA, IO, -3>(s, QA, cx, P, L, R0 - 3);
     strip_step<COLS, BETA, IO, -2>(s, QB, cx, P, L, R0 - 2);
     strip_step<COLS, BETA, IO, -1>(s, QA, cx, P, L, R0 - 1);
-    // main walk, two rows per trip so that values carried one row are renamed
-    // rather than copied.  The first trip is peeled: the loop is then entered
-    // only after the memory operations of a whole trip, as on every later
-    // trip, so the compiler's wait counts for the queued loads are exact
-    // rather than those of the store-free prologue.
+    // Main walk, several rows per trip so that values carried from row to row
+    // are renamed rather than copied: six rows with two float columns per
+    // lane (the input window spans six rows and the x-point windows three, so
+    // all of them rotate by renaming alone), two otherwise.  The first trip
+    // is peeled: the loop is then entered only after the memory operations of
+    // a whole trip, as on every later trip, so the compiler's wait counts for
+    // the queued loads are exact rather than those of the store-free prologue.
+    // (The two loop forms below compute the same thing; each kernel family
+    // takes the one its register allocation handles best -- measured: the
+    // one-column kernels keep in-flight loads out of the back-edge copies in
+    // the plain form, the two-column byte kernels fit three waves per SIMD in
+    // the trip form.)
+    constexpr int TRIP = (COLS == 2 && !io_out_u8(IO) && IO != kIoGeneric) ? 6 : 2;
     int R = R0;
-    if (R + 1 < R1) {
-        strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
-        strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
-        for (R += 2; R + 1 < R1; R += 2) {
+    if constexpr (COLS == 1) {
+        if (R + 1 < R1) {
             strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
             strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
+            for (R += 2; R + 1 < R1; R += 2) {
+                strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
+                strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
+            }
+        }
+    } else {
+        auto trip = [&](int r) {
+#pragma unroll
+            for (int k = 0; k < TRIP; k += 2) {
+                strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, r + k);
+                strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, r + k + 1);
+            }
+        };
+        if (R + TRIP - 1 < R1) {
+            trip(R);
+            for (R += TRIP; R + TRIP - 1 < R1; R += TRIP) trip(R);
+        }
+#pragma unroll
+        for (int k = 2; k < TRIP; k += 2) {
+            if (R + 1 < R1) {
+                strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
+                strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
+                R += 2;
+            }
         }
     }
     if (R < R1) strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
