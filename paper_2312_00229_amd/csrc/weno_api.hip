@@ -587,6 +587,11 @@ extern "C" int weno_zoom2x_batched(const weno_tensor_t* srcs, const weno_tensor_
 // --------------------------------------------------------------------------
 // cascade of doublings
 // --------------------------------------------------------------------------
+// row pitch (floats) of the float intermediates: a multiple of 4, so that
+// rows are 16-byte aligned and the forward kernel stores them with vector
+// stores (odd input widths would otherwise leave the first level unaligned)
+static int64_t cascade_pitch(int64_t w) { return (w + 3) / 4 * 4; }
+
 static void cascade_level_shape(const weno_tensor_t* src, int lvl, int64_t* h, int64_t* w)
 {
     *h = (int64_t)src->h << lvl;
@@ -600,7 +605,7 @@ extern "C" size_t weno_zoom2x_cascade_workspace(const weno_tensor_t* src, int32_
     for (int l = 1; l < levels; ++l) {
         int64_t h, w;
         cascade_level_shape(src, l, &h, &w);
-        const size_t bytes = (size_t)src->n * src->c * h * w * 4;
+        const size_t bytes = (size_t)src->n * src->c * h * cascade_pitch(w) * 4;
         total += (bytes + 255) / 256 * 256;
     }
     return total == 0 ? 256 : total;
@@ -642,10 +647,10 @@ extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t
             out.h = (int32_t)h;
             out.w = (int32_t)w;
             out.sw = 1;
-            out.sh = w;
-            out.sc = h * w;
-            out.sn = (int64_t)src->c * h * w;
-            const size_t bytes = (size_t)src->n * src->c * h * w * 4;
+            out.sh = cascade_pitch(w);
+            out.sc = h * out.sh;
+            out.sn = (int64_t)src->c * out.sc;
+            const size_t bytes = (size_t)src->n * src->c * h * out.sh * 4;
             off += (bytes + 255) / 256 * 256;
             if (wz_overlap(&out, dst) || wz_overlap(&out, src)) return WENO_EOVERLAP;
         }

@@ -68,57 +68,97 @@ __device__ __forceinline__ float weno1d(float vm, float v0, float v1, float v2, 
     return __builtin_fmaf(al1 * rcp(al0 + al1), p1 - p0, p0);
 }
 
-// AXIS 0: resample along the rows (output row r <- input rows), AXIS 1: along the columns
-template <int AXIS, int BETA>
-__global__ __launch_bounds__(256) void resample_kernel(ResampleArgs a)
+// Source position of one output sample along an axis: the interval
+// [x_i, x_{i+1}] and t in (0, 1), or a node copy of sample i (t < 0).
+struct SamplePos {
+    int32_t i;
+    float t;
+};
+
+// Positions j (n_in - 1)/(n_out - 1) = i + t of an axis, one thread each,
+// worked out in integers so that nodes are exact; t is rem/den rounded once.
+__global__ __launch_bounds__(256) void positions_kernel(SamplePos* __restrict__ pos, int n_in, int n_out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_out) return;
+    SamplePos p;
+    p.i = 0;
+    p.t = -1.0f;
+    if (n_out > 1 && n_in > 1) {
+        const uint64_t num = (uint64_t)j * (uint64_t)(n_in - 1);
+        const uint64_t den = (uint64_t)(n_out - 1);
+        int i = (int)(num / den);
+        const uint64_t rem = num - (uint64_t)i * den;
+        if (i > n_in - 2) {
+            p.i = n_in - 1;          // the last node
+        } else if (rem == 0) {
+            p.i = i;                 // a node
+        } else {
+            p.i = i;
+            p.t = (float)((double)rem / (double)den);
+        }
+    }
+    pos[j] = p;
+}
+
+// AXIS 0: resample along the rows (output row r <- input rows of column c),
+// AXIS 1: along the columns (output column c <- input columns of row r).
+template <int AXIS, int BETA, bool IN_U8, bool OUT_U8>
+__global__ __launch_bounds__(256) void resample_kernel(ResampleArgs a, const SamplePos* __restrict__ pos)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (c >= a.out_w) return;
     const int plane = blockIdx.z;
     const int n = plane / a.C, ch = plane - n * a.C;
-    const uint8_t* src = a.src + n * a.s_n + ch * a.s_c;
-    uint8_t* dst = a.dst + n * a.d_n + ch * a.d_c;
-    const int j = AXIS == 0 ? r : c;
+    const SamplePos p = pos[AXIS == 0 ? r : c];
     const int n_in = AXIS == 0 ? a.in_h : a.in_w;
-    const int n_out = AXIS == 0 ? a.out_h : a.out_w;
-    // position j (n_in - 1)/(n_out - 1) = i + t
-    int i = 0;
-    uint64_t rem = 0, den = 1;
-    if (n_out > 1 && n_in > 1) {
-        const uint64_t num = (uint64_t)j * (uint64_t)(n_in - 1);
-        den = (uint64_t)(n_out - 1);
-        i = (int)(num / den);
-        rem = num - (uint64_t)i * den;
-        if (i > n_in - 2) {  // the last node: x = n_in - 1
-            i = n_in - 2;
-            rem = den;
-        }
-    }
+    // the input line the samples come from and the stride along it; offsets
+    // within a plane are 32-bit (planes span less than 2^31 bytes)
+    const uint8_t* plane_in = a.src + n * a.s_n + ch * a.s_c;
+    const uint32_t line = AXIS == 0 ? (uint32_t)c * (uint32_t)a.s_w : (uint32_t)r * (uint32_t)a.s_h;
+    const uint32_t step = (uint32_t)(AXIS == 0 ? a.s_h : a.s_w);
     auto ld = [&](int k) -> float {
         const int kc = k < 0 ? 0 : (k >= n_in ? n_in - 1 : k);
-        const int64_t off = AXIS == 0 ? (int64_t)kc * a.s_h + (int64_t)c * a.s_w : (int64_t)r * a.s_h + (int64_t)kc * a.s_w;
-        return a.in_u8 ? (float)src[off] : *(const float*)(src + off);
+        const uint8_t* q = plane_in + (line + (uint32_t)kc * step);
+        if constexpr (IN_U8) return (float)*q;
+        else return *(const float*)q;
     };
     float u;
-    if (rem == 0) {
-        u = ld(i);
-    } else if (rem == den) {
-        u = ld(i + 1);
-    } else {
-        const float t = (float)((double)rem / (double)den);
-        u = weno1d<BETA>(ld(i - 1), ld(i), ld(i + 1), ld(i + 2), t, a.eps, a.beta);
-    }
-    const int64_t doff = (int64_t)r * a.d_h + (int64_t)c * a.d_w;
-    if (a.out_u8) {
-        dst[doff] = (uint8_t)quant_u8(u * a.out_scale);
-    } else {
-        *(float*)(dst + doff) = u * a.out_scale;
-    }
+    if (p.t < 0.0f) u = ld(p.i);
+    else u = weno1d<BETA>(ld(p.i - 1), ld(p.i), ld(p.i + 1), ld(p.i + 2), p.t, a.eps, a.beta);
+    uint8_t* o = a.dst + n * a.d_n + ch * a.d_c + ((uint32_t)r * (uint32_t)a.d_h + (uint32_t)c * (uint32_t)a.d_w);
+    if constexpr (OUT_U8) *o = (uint8_t)quant_u8(u * a.out_scale);
+    else *(float*)o = u * a.out_scale;
 }
 
+template <int AXIS, int BETA>
+void launch_typed(const ResampleArgs& a, const SamplePos* pos, dim3 grid, hipStream_t st)
+{
+    if (a.in_u8 && a.out_u8)
+        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, true, true>), grid, dim3(256), 0, st, a, pos);
+    else if (a.in_u8)
+        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, true, false>), grid, dim3(256), 0, st, a, pos);
+    else if (a.out_u8)
+        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, false, true>), grid, dim3(256), 0, st, a, pos);
+    else
+        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, false, false>), grid, dim3(256), 0, st, a, pos);
+}
+
+// bytes of a position table of n entries (256-byte aligned)
+size_t positions_bytes(int64_t n) { return (size_t)((n * (int64_t)sizeof(SamplePos) + 255) / 256 * 256); }
+
+int launch_positions(SamplePos* pos, int n_in, int n_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(positions_kernel, dim3((n_out + 255) / 256), dim3(256), 0, st, pos, n_in, n_out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? WENO_OK : wz_hip_error(e, "positions_kernel launch");
+}
+
+// One pass along `axis` (0: rows, 1: columns); `pos` holds the positions of
+// the resampled axis (dst->h entries for rows, dst->w for columns).
 int launch_resample(int axis, const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, double h,
-                    hipStream_t st)
+                    const SamplePos* pos, hipStream_t st)
 {
     ResampleArgs a;
     const int64_t ei = wz_esize(src->dtype), eo = wz_esize(dst->dtype);
@@ -140,16 +180,20 @@ int launch_resample(int axis, const weno_tensor_t* src, const weno_tensor_t* dst
     dim3 grid((dst->w + 255) / 256, dst->h, dst->n * dst->c);
     const bool b2 = p->beta == 2.0f;
     if (axis == 0) {
-        if (b2) hipLaunchKernelGGL((resample_kernel<0, 2>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((resample_kernel<0, kBetaGeneral>), grid, dim3(256), 0, st, a);
+        if (b2) launch_typed<0, 2>(a, pos, grid, st);
+        else launch_typed<0, kBetaGeneral>(a, pos, grid, st);
     } else {
-        if (b2) hipLaunchKernelGGL((resample_kernel<1, 2>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((resample_kernel<1, kBetaGeneral>), grid, dim3(256), 0, st, a);
+        if (b2) launch_typed<1, 2>(a, pos, grid, st);
+        else launch_typed<1, kBetaGeneral>(a, pos, grid, st);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wz_hip_error(e, "resample_kernel launch");
     return WENO_OK;
 }
+
+// row pitch (floats) of workspace planes: a multiple of 4, so that rows are
+// 16-byte aligned and the forward kernel stores them with vector stores
+int64_t f32_pitch(int64_t w) { return (w + 3) / 4 * 4; }
 
 weno_tensor_t planar_f32(void* data, int n, int c, int h, int w)
 {
@@ -157,11 +201,12 @@ weno_tensor_t planar_f32(void* data, int n, int c, int h, int w)
     t.data = data;
     t.dtype = WENO_F32;
     t.n = n; t.c = c; t.h = h; t.w = w;
-    t.sw = 1; t.sh = w; t.sc = (int64_t)h * w; t.sn = (int64_t)c * h * w;
+    t.sw = 1; t.sh = f32_pitch(w); t.sc = (int64_t)h * t.sh; t.sn = (int64_t)c * t.sc;
     return t;
 }
 
-size_t aligned_bytes(int64_t elems) { return (size_t)((elems * 4 + 255) / 256 * 256); }
+// bytes of planar float planes of h x w (pitched rows), 256-byte aligned
+size_t planes_bytes(int64_t planes, int64_t h, int64_t w) { return (size_t)((planes * h * f32_pitch(w) * 4 + 255) / 256 * 256); }
 
 // doublings needed so that 2^k (n - 1) + 1 reaches the target on every axis longer than one sample
 int zoom_levels(const weno_tensor_t* src, const weno_tensor_t* dst)
@@ -181,16 +226,45 @@ int check_resample_pair(const weno_tensor_t* src, const weno_tensor_t* dst)
     if (rc) return rc;
     if (src->n != dst->n || src->c != dst->c) return WENO_EINVAL;
     if ((int64_t)src->n * src->c > 65535 || dst->h > 65535) return WENO_EINVAL;
+    // offsets within a plane are 32-bit: every plane (and the float
+    // intermediate of the row pass) must span less than 2^31 bytes
+    if (wz_plane_extent(src) >= (1ll << 31) || wz_plane_extent(dst) >= (1ll << 31)) return WENO_EINVAL;
     if (wz_overlap(src, dst)) return WENO_EOVERLAP;
     return WENO_OK;
 }
 
 }  // namespace
 
+// workspace of the resampler: the row pass's float planes (dst->h x src->w),
+// then the position tables of the rows and of the columns
+static size_t resample_bytes(const weno_tensor_t* src, const weno_tensor_t* dst, int64_t in_w)
+{
+    return planes_bytes((int64_t)src->n * src->c, dst->h, in_w) + positions_bytes(dst->h) + positions_bytes(dst->w);
+}
+
+// the row pass, then the column pass, of src (any dtype, in_h x in_w) into dst
+static int run_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, double h,
+                        uint8_t* ws, hipStream_t st)
+{
+    if ((int64_t)dst->h * f32_pitch(src->w) * 4 >= (1ll << 31)) return WENO_EINVAL;   // 32-bit plane offsets
+    weno_tensor_t tmp = planar_f32(ws, src->n, src->c, dst->h, src->w);
+    if (wz_overlap(&tmp, src) || wz_overlap(&tmp, dst)) return WENO_EOVERLAP;
+    uint8_t* tabs = ws + planes_bytes((int64_t)src->n * src->c, dst->h, src->w);
+    SamplePos* rows = (SamplePos*)tabs;
+    SamplePos* cols = (SamplePos*)(tabs + positions_bytes(dst->h));
+    int rc = launch_positions(rows, src->h, dst->h, st);
+    if (rc) return rc;
+    rc = launch_positions(cols, src->w, dst->w, st);
+    if (rc) return rc;
+    rc = launch_resample(0, src, &tmp, p, h, rows, st);
+    if (rc) return rc;
+    return launch_resample(1, &tmp, dst, p, h, cols, st);
+}
+
 extern "C" size_t weno_resample_workspace(const weno_tensor_t* src, const weno_tensor_t* dst)
 {
     if (check_resample_pair(src, dst) != WENO_OK) return 0;
-    return aligned_bytes((int64_t)src->n * src->c * dst->h * src->w);
+    return resample_bytes(src, dst, src->w);
 }
 
 extern "C" int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p,
@@ -202,12 +276,7 @@ extern "C" int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst,
     if (rc) return rc;
     if (!d_workspace) return WENO_EINVAL;
     if (ws_bytes < weno_resample_workspace(src, dst)) return WENO_ENOSPC;
-    weno_tensor_t tmp = planar_f32(d_workspace, src->n, src->c, dst->h, src->w);
-    if (wz_overlap(&tmp, src) || wz_overlap(&tmp, dst)) return WENO_EOVERLAP;
-    hipStream_t st = (hipStream_t)hip_stream;
-    rc = launch_resample(0, src, &tmp, p, p->h, st);
-    if (rc) return rc;
-    return launch_resample(1, &tmp, dst, p, p->h, st);
+    return run_resample(src, dst, p, p->h, (uint8_t*)d_workspace, (hipStream_t)hip_stream);
 }
 
 extern "C" size_t weno_zoom_to_workspace(const weno_tensor_t* src, const weno_tensor_t* dst)
@@ -217,12 +286,11 @@ extern "C" size_t weno_zoom_to_workspace(const weno_tensor_t* src, const weno_te
     size_t total = 0;
     int64_t h = src->h, w = src->w;
     for (int l = 0; l < k; ++l) {
-        total += aligned_bytes((int64_t)src->n * src->c * (2 * h) * (2 * w));
+        total += planes_bytes((int64_t)src->n * src->c, 2 * h, 2 * w);
         h = 2 * h - 1;
         w = 2 * w - 1;
     }
-    total += aligned_bytes((int64_t)src->n * src->c * dst->h * w);
-    return total;
+    return total + resample_bytes(src, dst, w);
 }
 
 int wz_launch_fwd(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, hipStream_t st, int rows,
@@ -246,7 +314,7 @@ extern "C" int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, 
     size_t off = 0;
     for (int l = 0; l < k; ++l) {
         weno_tensor_t out = planar_f32(ws + off, src->n, src->c, 2 * cur.h, 2 * cur.w);
-        off += aligned_bytes((int64_t)src->n * src->c * out.h * out.w);
+        off += planes_bytes((int64_t)src->n * src->c, out.h, out.w);
         if (wz_overlap(&out, src) || wz_overlap(&out, dst)) return WENO_EOVERLAP;
         rc = wz_check_pair(&cur, &out, 2);
         if (rc) return rc;
@@ -265,9 +333,5 @@ extern "C" int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, 
     }
     weno_params_t rp = *p;
     rp.h = (float)(p->h * std::ldexp(1.0, -k));
-    weno_tensor_t tmp = planar_f32(ws + off, src->n, src->c, dst->h, cur.w);
-    if (wz_overlap(&tmp, dst) || wz_overlap(&tmp, src)) return WENO_EOVERLAP;
-    rc = launch_resample(0, &cur, &tmp, &rp, rp.h, st);
-    if (rc) return rc;
-    return launch_resample(1, &tmp, dst, &rp, rp.h, st);
+    return run_resample(&cur, dst, &rp, rp.h, ws + off, st);
 }

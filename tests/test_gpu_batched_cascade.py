@@ -38,9 +38,10 @@ def test_batched_f32_against_oracle(gpu):
         assert np.abs(y.cpu().numpy() - ref).max() <= TOL
 
 
-def test_cascade_three_levels(gpu):
+@pytest.mark.parametrize("hw", [(32, 32), (21, 37)])   # odd widths use pitched intermediates
+def test_cascade_three_levels(gpu, hw):
     gpu.set_launch_config(64, 2)
-    img = pixel_art(32, 32, seed=1, block=8, n_lines=4)
+    img = pixel_art(*hw, seed=1, block=8, n_lines=4)
     x = torch.tensor(img, device="cuda").permute(2, 0, 1)
     yf = gpu.zoom2x_cascade(x, 3, out_dtype=torch.float32).permute(1, 2, 0).cpu().numpy()
     ref = oracle.cascade(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 3)

@@ -68,3 +68,28 @@ def test_quality_protocol_runs(gpu):
         assert 10.0 < p < 80.0 and 0.0 < s <= 1.0
     up = gpu.zoom_to(img[:, ::2, ::2].contiguous(), 129, 193)
     assert torch.equal(up[:, ::2, ::2], img[:, ::2, ::2])
+
+
+@pytest.mark.parametrize("pair", ["u8->f32", "f32->u8"])
+def test_resample_mixed_dtypes(gpu, pair):
+    V = random_plane(37, 53, seed=4, kind="steps") * 0.6 + 0.4 * random_plane(37, 53, seed=5)
+    if pair == "u8->f32":
+        img = (V * 255.0).round().astype(np.uint8)
+        got = gpu.resample(_t(img, np.uint8), 71, 30, out_dtype=torch.float32).cpu().numpy()
+        ref = R.tensor_resample(img.astype(np.float64) / 255.0, 71, 30)
+        assert np.abs(got - ref).max() <= TOL
+    else:
+        V32 = V.astype(np.float32)
+        got = gpu.resample(_t(V32), 71, 30, out_dtype=torch.uint8).cpu().numpy()
+        ref = R.tensor_resample(V32.astype(np.float64), 71, 30)
+        ties, errors = u8_compare(got, ref)
+        assert errors == 0
+
+
+@pytest.mark.parametrize("shape,out", [((41, 77), (150, 301)), ((25, 33), (97, 40))])
+def test_zoom_to_odd_widths_two_levels(gpu, shape, out):
+    # two doublings through pitched float intermediates of odd widths
+    V = random_plane(*shape, seed=17, kind="steps") * 0.5 + 0.5 * random_plane(*shape, seed=18)
+    got = gpu.zoom_to(_t(V), *out).cpu().numpy()
+    ref = R.zoom_to(V.astype(np.float32).astype(np.float64), *out)
+    assert np.abs(got - ref).max() <= 3 * TOL
