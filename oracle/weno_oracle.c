@@ -367,7 +367,9 @@ static void adjoint_pass(wo_state* s, fgrid* gF, fgrid gS[4], int phase, int lo,
             for (int k = 0; k < 4; ++k) {
                 double w = a[k] / asum;
                 double pk = AT(s->P[k], i, j);
-                double gt = -s->beta * g * w * (pk - u) / AT(s->T[k], i, j);
+                /* with beta = 0 the weights 0.5 / t^0 do not depend on t
+                 * (eq. alpha), so the term vanishes, also where t = 0 */
+                double gt = s->beta == 0.0 ? 0.0 : -s->beta * g * w * (pk - u) / AT(s->T[k], i, j);
                 AT(gP[k], i, j) += g * w;
                 AT(gS[k], i, j) += gt;
                 for (int q = 0; q < 4; ++q) AT(gS[k], i + nb[q][0], j + nb[q][1]) += s->nbw * gt;

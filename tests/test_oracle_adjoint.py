@@ -41,3 +41,21 @@ def test_torch_gradcheck_16x16():
     rng = np.random.default_rng(2)
     V = torch.tensor(rng.random((16, 16)), requires_grad=True)
     assert torch.autograd.gradcheck(lambda v: torch_ref.zoom2x(v, beta=2.0), (V,), eps=1e-6, atol=1e-5)
+
+
+@pytest.mark.parametrize("kind", ["binary", "steps"])
+def test_adjoint_beta0_is_the_transpose(oracle_mod, kind):
+    # beta = 0 makes every weight 0.5 / t^0 = 0.5, so the doubling is a
+    # linear map A and its adjoint is exactly A^T: <A d, g> = <d, A^T g> for
+    # any d, with no finite-difference error.  k_eps = 0 leaves the
+    # indicators of flat regions at 0, where the weights must stay constant.
+    rng = np.random.default_rng(7)
+    V = random_plane(11, 14, seed=3, kind=kind)
+    D = rng.standard_normal(V.shape)
+    G = rng.standard_normal((22, 28))
+    gv = oracle_mod.backward(V, G, beta=0.0, keps=0.0)
+    assert np.isfinite(gv).all()
+    lhs = (oracle_mod.zoom2x(D, beta=0.0, keps=0.0) * G).sum()
+    assert abs(lhs - (D * gv).sum()) <= 1e-12 * max(1.0, abs(lhs))
+    # and eps plays no part in it
+    assert np.array_equal(gv, oracle_mod.backward(V, G, beta=0.0, keps=1e-8))
