@@ -154,7 +154,8 @@ int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t* dst, int3
  * copied exactly; samples beyond the ends are clamped.  eps = k_eps h^2 as for
  * the doubling (nbw is unused).
  *   d_workspace: DEVICE memory of at least weno_resample_workspace(src, dst)
- *                bytes (an FP32 (n, c, H, w) intermediate).
+ *                bytes (an FP32 (n, c, H, w + 3) intermediate, edge columns
+ *                replicated, and the positions of the H rows and W columns).
  */
 size_t weno_resample_workspace(const weno_tensor_t* src, const weno_tensor_t* dst);
 int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, void* d_workspace,

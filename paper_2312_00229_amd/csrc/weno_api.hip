@@ -248,7 +248,9 @@ FwdParams wz_fwd_params(const weno_params_t* p, int in_u8, int out_u8)
     const double vs = in_u8 ? 255.0 : 1.0;  // kernel value scale relative to [0,1]
     const double eps = (double)p->k_eps * (double)p->h * (double)p->h * vs * vs;
     FwdParams P;
-    P.eps_hat = (float)(eps * (12.0 / 13.0) / (1.0 + 4.0 * w));
+    // with beta = 0 the weights are t^0 = 1 whatever the indicator, and eps
+    // (which may then be 0) only has to keep t away from 0 for log2
+    P.eps_hat = p->beta == 0.0f ? 1.0f : (float)(eps * (12.0 / 13.0) / (1.0 + 4.0 * w));
     P.w = (float)w;
     P.beta = p->beta;
     const double os = out_u8 ? 255.0 : 1.0;

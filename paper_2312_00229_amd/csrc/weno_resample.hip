@@ -15,12 +15,12 @@
 //   SI_1    = b1^2 - 2 b1 b2 + (16/3) b2^2
 // Output sample j of an axis of n_out samples sits at x_j = j (n_in - 1)/(n_out - 1)
 // (end points aligned), computed in integers so that t is exact to FP32
-// rounding; samples on input nodes are copied.  One thread per output
-// element; the two passes (rows, then columns) go through an FP32
-// intermediate in the caller's workspace.
+// rounding; samples on input nodes are copied.  The two passes (rows, then
+// columns) go through an FP32 intermediate in the caller's workspace.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "weno_internal.h"
 #include "weno_zoom.h"
@@ -29,61 +29,59 @@ using namespace wz;
 
 namespace {
 
-struct ResampleArgs {
-    const uint8_t* src;
-    uint8_t* dst;
-    int32_t C;
-    int32_t in_h, in_w, out_h, out_w;   // along the resampled axis: in -> out; the other axis is equal
-    int64_t s_n, s_c, s_h, s_w;         // byte strides
-    int64_t d_n, d_c, d_h, d_w;
-    int32_t in_u8, out_u8;
-    float eps;        // in the kernel's value scale
-    float beta;
-    float out_scale;  // output value = u * out_scale
-};
-
+// The blend on [x_i, x_{i+1}] with the differences A1 = 2 a1, A2 = 2 a2,
+// B1 = 2 b1, B2 = 2 b2 of the header's coefficients:
+//   p_i = v_i + (t/2)(A1 + A2 t),   p_{i+1} = v_{i+1} + (s/2)(B1 + B2 s),
+//   4 (eps + SI_0) = E_0 = 4 eps + A1^2 + 2 A1 A2 + (16/3) A2^2,
+//   4 (eps + SI_1) = E_1 = 4 eps + B1^2 - 2 B1 B2 + (16/3) B2^2,
+// and, dividing alpha_0 + alpha_1 by alpha_1,
+//   omega_1 = 1 / (1 + (C_0/C_1) (E_1/E_0)^beta),   u = p_i + omega_1 (p_{i+1} - p_i),
+// two reciprocals per sample.  E_0, E_1 >= 4 eps > 0 (for beta = 0 the host
+// passes eps = 1: the weights are then C_s whatever the indicators).  A node
+// (t = 0, wmask = 0) gets omega_1 = 0 (1/(1 + k g) <= 1 is finite), so
+// u = p_i = v_i exactly.
 template <int BETA>
-__device__ __forceinline__ float weno1d(float vm, float v0, float v1, float v2, float t, float eps, float beta)
+__device__ __forceinline__ float blend(float vm, float v0, float v1, float v2, float t, float s, float ht, float hs,
+                                       float k, float eps4, float beta, float wmask = 1.0f)
 {
-    const float a1 = 0.5f * (v1 - vm);
-    const float a2 = 0.5f * ((v1 + vm) - 2.0f * v0);
-    const float b1 = 0.5f * (v2 - v0);
-    const float b2 = 0.5f * ((v2 + v0) - 2.0f * v1);
-    const float s = t - 1.0f;
-    const float p0 = __builtin_fmaf(t, __builtin_fmaf(t, a2, a1), v0);
-    const float p1 = __builtin_fmaf(s, __builtin_fmaf(s, b2, b1), v1);
-    const float si0 = __builtin_fmaf(a1, a1, a2 * __builtin_fmaf(a2, 16.0f / 3.0f, 2.0f * a1));
-    const float si1 = __builtin_fmaf(b1, b1, b2 * __builtin_fmaf(b2, 16.0f / 3.0f, -2.0f * b1));
-    const float c0 = (2.0f - t) * (1.0f / 3.0f), c1 = (t + 1.0f) * (1.0f / 3.0f);
-    float al0, al1;
-    if constexpr (BETA == 2) {
-        const float r0 = rcp(eps + si0), r1 = rcp(eps + si1);
-        al0 = c0 * (r0 * r0);
-        al1 = c1 * (r1 * r1);
-    } else {
-        al0 = c0 * __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(eps + si0));
-        al1 = c1 * __builtin_amdgcn_exp2f(-beta * __builtin_amdgcn_logf(eps + si1));
-    }
-    // u = p0 + omega_1 (p1 - p0)
-    return __builtin_fmaf(al1 * rcp(al0 + al1), p1 - p0, p0);
+    const float A1 = v1 - vm;
+    const float A2 = __builtin_fmaf(v0, -2.0f, v1 + vm);
+    const float B1 = v2 - v0;
+    const float B2 = __builtin_fmaf(v1, -2.0f, v2 + v0);
+    const float p0 = __builtin_fmaf(ht, __builtin_fmaf(t, A2, A1), v0);
+    const float p1 = __builtin_fmaf(hs, __builtin_fmaf(s, B2, B1), v1);
+    const float E0 = __builtin_fmaf(A2, __builtin_fmaf(A2, 16.0f / 3.0f, A1 + A1), __builtin_fmaf(A1, A1, eps4));
+    const float E1 = __builtin_fmaf(B2, __builtin_fmaf(B2, 16.0f / 3.0f, -(B1 + B1)), __builtin_fmaf(B1, B1, eps4));
+    const float q = E1 * rcp(E0);
+    float g;
+    if constexpr (BETA == 2) g = q * q;
+    else g = __builtin_amdgcn_exp2f(beta * __builtin_amdgcn_logf(q));
+    const float w1 = rcp(__builtin_fmaf(k, g, 1.0f)) * wmask;
+    return __builtin_fmaf(w1, p1 - p0, p0);
 }
 
 // Source position of one output sample along an axis: the interval
-// [x_i, x_{i+1}] and t in (0, 1), or a node copy of sample i (t < 0).
+// [x_i, x_{i+1}], t in (0, 1) and k = C_0(t)/C_1(t), or a copy of node i
+// (node = 1, t = 0).
 struct SamplePos {
     int32_t i;
     float t;
+    float k;
+    int32_t node;
 };
 
 // Positions j (n_in - 1)/(n_out - 1) = i + t of an axis, one thread each,
-// worked out in integers so that nodes are exact; t is rem/den rounded once.
+// worked out in integers so that nodes are exact; t and k are rounded once
+// from exact ratios.
 __global__ __launch_bounds__(256) void positions_kernel(SamplePos* __restrict__ pos, int n_in, int n_out)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_out) return;
     SamplePos p;
     p.i = 0;
-    p.t = -1.0f;
+    p.t = 0.0f;
+    p.k = 2.0f;
+    p.node = 1;
     if (n_out > 1 && n_in > 1) {
         const uint64_t num = (uint64_t)j * (uint64_t)(n_in - 1);
         const uint64_t den = (uint64_t)(n_out - 1);
@@ -95,54 +93,188 @@ __global__ __launch_bounds__(256) void positions_kernel(SamplePos* __restrict__ 
             p.i = i;                 // a node
         } else {
             p.i = i;
+            p.node = 0;
             p.t = (float)((double)rem / (double)den);
+            // C_0/C_1 = (2 - t)/(t + 1) = (2 den - rem)/(den + rem)
+            p.k = (float)((double)(2 * den - rem) / (double)(den + rem));
         }
     }
     pos[j] = p;
 }
 
-// AXIS 0: resample along the rows (output row r <- input rows of column c),
-// AXIS 1: along the columns (output column c <- input columns of row r).
-template <int AXIS, int BETA, bool IN_U8, bool OUT_U8>
-__global__ __launch_bounds__(256) void resample_kernel(ResampleArgs a, const SamplePos* __restrict__ pos)
+// Work split of both passes: a wave owns kCpl columns per lane (64 apart, so
+// every memory operation of the wave is one coalesced row segment) and a run
+// of kRun output rows; setup is paid once per 64 * kCpl * kRun outputs.
+constexpr int kCpl = 2;
+constexpr int kRun = 16;
+
+// The row pass writes rows of in_w + 3 samples: padded column x holds input
+// column clamp(x - 1, 0, in_w - 1), so the column pass finds the taps
+// i - 1 .. i + 2 of any interval at padded columns i .. i + 3, unclamped.
+constexpr int kPadCols = 3;
+
+struct RowPassArgs {
+    const uint8_t* src;       // input planes (any dtype, byte strides below)
+    uint8_t* tmp;             // padded float planes
+    int64_t s_n, s_c;
+    uint32_t s_h, s_w;        // input row and column strides
+    uint32_t src_extent;      // bytes spanned by one input plane
+    uint32_t t_h;             // padded row pitch (bytes)
+    uint32_t t_plane;         // bytes per padded plane
+    int32_t C, in_h, in_w, out_h;
+    int32_t chunks, runs;     // column chunks of 64 * kCpl padded columns, row runs of kRun
+    float eps4, beta;
+};
+
+// AXIS 0: output row r of column x <- input rows i - 1 .. i + 2 of r's
+// interval.  Every tap row is uniform over the wave.
+template <int BETA, bool IN_U8>
+__global__ __launch_bounds__(256) void rows_pass_kernel(RowPassArgs a, const SamplePos* __restrict__ pos)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    if (c >= a.out_w) return;
-    const int plane = blockIdx.z;
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wave >= a.chunks * a.runs) return;
+    const int lane = threadIdx.x & 63;
+    const int run = wave / a.chunks, chunk = wave - run * a.chunks;
+    const int plane = blockIdx.y;
     const int n = plane / a.C, ch = plane - n * a.C;
-    const SamplePos p = pos[AXIS == 0 ? r : c];
-    const int n_in = AXIS == 0 ? a.in_h : a.in_w;
-    // the input line the samples come from and the stride along it; offsets
-    // within a plane are 32-bit (planes span less than 2^31 bytes)
-    const uint8_t* plane_in = a.src + n * a.s_n + ch * a.s_c;
-    const uint32_t line = AXIS == 0 ? (uint32_t)c * (uint32_t)a.s_w : (uint32_t)r * (uint32_t)a.s_h;
-    const uint32_t step = (uint32_t)(AXIS == 0 ? a.s_h : a.s_w);
-    auto ld = [&](int k) -> float {
-        const int kc = k < 0 ? 0 : (k >= n_in ? n_in - 1 : k);
-        const uint8_t* q = plane_in + (line + (uint32_t)kc * step);
-        if constexpr (IN_U8) return (float)*q;
-        else return *(const float*)q;
+    const rsrc_t src = make_rsrc(a.src + n * a.s_n + ch * a.s_c, a.src_extent);
+    const rsrc_t dst = make_rsrc(a.tmp + (size_t)plane * a.t_plane, a.t_plane);
+    const int padded = a.in_w + kPadCols;
+    uint32_t vin[kCpl], vout[kCpl];
+#pragma unroll
+    for (int j = 0; j < kCpl; ++j) {
+        const int x = chunk * (64 * kCpl) + lane + 64 * j;
+        const int xc = min(max(x - 1, 0), a.in_w - 1);
+        vin[j] = x < padded ? (uint32_t)xc * a.s_w : kOob;
+        vout[j] = x < padded ? (uint32_t)x * 4u : kOob;
+    }
+    constexpr float kScale = IN_U8 ? 1.0f / 255.0f : 1.0f;   // the padded planes are on the [0,1] scale of u8
+    // raw taps (bytes stay bytes until the row is used, so that no wait
+    // follows the loads)
+    using raw = typename std::conditional<IN_U8, uint8_t, float>::type;
+    auto ld = [&](uint32_t voff, uint32_t soff) -> raw {
+        if constexpr (IN_U8) return __builtin_amdgcn_raw_buffer_load_b8(src, (int)voff, (int)soff, 0);
+        else return buf_ld_f32(src, voff, soff);
     };
-    float u;
-    if (p.t < 0.0f) u = ld(p.i);
-    else u = weno1d<BETA>(ld(p.i - 1), ld(p.i), ld(p.i + 1), ld(p.i + 2), p.t, a.eps, a.beta);
-    uint8_t* o = a.dst + n * a.d_n + ch * a.d_c + ((uint32_t)r * (uint32_t)a.d_h + (uint32_t)c * (uint32_t)a.d_w);
-    if constexpr (OUT_U8) *o = (uint8_t)quant_u8(u * a.out_scale);
-    else *(float*)o = u * a.out_scale;
+    // the taps of output row r, loaded one row ahead of their use
+    struct Taps {
+        raw v[4][kCpl];
+        float t, k;
+    };
+    auto load = [&](Taps& T, int r) {
+        const SamplePos p = pos[r];
+        const uint32_t s0 = (uint32_t)p.i * a.s_h;
+        // a node collapses all four taps onto its row: the blend of four equal
+        // (finite) values is that value, exactly
+        const bool node = p.node != 0;
+        const uint32_t sm = node ? s0 : (uint32_t)max(p.i - 1, 0) * a.s_h;
+        const uint32_t s1 = node ? s0 : s0 + a.s_h;
+        const uint32_t s2 = node ? s0 : (uint32_t)min(p.i + 2, a.in_h - 1) * a.s_h;
+#pragma unroll
+        for (int j = 0; j < kCpl; ++j) {
+            T.v[0][j] = ld(vin[j], sm);
+            T.v[1][j] = ld(vin[j], s0);
+            T.v[2][j] = ld(vin[j], s1);
+            T.v[3][j] = ld(vin[j], s2);
+        }
+        T.t = p.t;
+        T.k = p.k;
+    };
+    auto emit = [&](const Taps& T, int r) {
+        const float t = T.t, s = t - 1.0f, ht = 0.5f * t, hs = 0.5f * s;
+        const uint32_t so = (uint32_t)r * a.t_h;
+#pragma unroll
+        for (int j = 0; j < kCpl; ++j)
+            buf_st_f32(blend<BETA>((float)T.v[0][j], (float)T.v[1][j], (float)T.v[2][j], (float)T.v[3][j], t, s, ht,
+                                   hs, T.k, a.eps4, a.beta) *
+                           kScale,
+                       dst, vout[j], so);
+    };
+    const int r0 = run * kRun, r1 = min(r0 + kRun, a.out_h);
+    Taps A, B;
+    int r = r0;
+    load(A, r);
+    for (; r + 2 <= r1; r += 2) {
+        load(B, r + 1);
+        emit(A, r);
+        load(A, min(r + 2, r1 - 1));
+        emit(B, r + 1);
+    }
+    if (r < r1) emit(A, r);
 }
 
-template <int AXIS, int BETA>
-void launch_typed(const ResampleArgs& a, const SamplePos* pos, dim3 grid, hipStream_t st)
+struct ColPassArgs {
+    const uint8_t* tmp;       // padded float planes
+    uint8_t* dst;             // output planes (any dtype, byte strides below)
+    int64_t d_n, d_c;
+    uint32_t d_h, d_w;
+    uint32_t d_extent;        // bytes spanned by one output plane
+    uint32_t t_h, t_plane;
+    int32_t C, out_h, out_w;
+    int32_t chunks, runs;     // column chunks of 64 * kCpl output columns, row runs of kRun
+    float eps4, beta;
+};
+
+// AXIS 1: output column c of row r <- padded columns i .. i + 3 of row r,
+// i the interval of c.  Positions and tap offsets are per lane, loaded once
+// per run.
+template <int BETA, bool OUT_U8>
+__global__ __launch_bounds__(256) void cols_pass_kernel(ColPassArgs a, const SamplePos* __restrict__ pos)
 {
-    if (a.in_u8 && a.out_u8)
-        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, true, true>), grid, dim3(256), 0, st, a, pos);
-    else if (a.in_u8)
-        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, true, false>), grid, dim3(256), 0, st, a, pos);
-    else if (a.out_u8)
-        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, false, true>), grid, dim3(256), 0, st, a, pos);
-    else
-        hipLaunchKernelGGL((resample_kernel<AXIS, BETA, false, false>), grid, dim3(256), 0, st, a, pos);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wave >= a.chunks * a.runs) return;
+    const int lane = threadIdx.x & 63;
+    const int run = wave / a.chunks, chunk = wave - run * a.chunks;
+    const int plane = blockIdx.y;
+    const int n = plane / a.C, ch = plane - n * a.C;
+    const rsrc_t src = make_rsrc(a.tmp + (size_t)plane * a.t_plane, a.t_plane);
+    const rsrc_t dst = make_rsrc(a.dst + n * a.d_n + ch * a.d_c, a.d_extent);
+    uint32_t vtap[kCpl], vout[kCpl];
+    float t[kCpl], s[kCpl], ht[kCpl], hs[kCpl], k[kCpl], wmask[kCpl];
+#pragma unroll
+    for (int j = 0; j < kCpl; ++j) {
+        const int c = chunk * (64 * kCpl) + lane + 64 * j;
+        const SamplePos p = pos[min(c, a.out_w - 1)];
+        vtap[j] = (uint32_t)p.i * 4u;
+        vout[j] = c < a.out_w ? (uint32_t)c * a.d_w : kOob;
+        wmask[j] = p.node ? 0.0f : 1.0f;
+        t[j] = p.t;
+        s[j] = p.t - 1.0f;
+        ht[j] = 0.5f * t[j];
+        hs[j] = 0.5f * s[j];
+        k[j] = p.k;
+    }
+    struct Taps {
+        float v[4][kCpl];
+    };
+    auto load = [&](Taps& T, int r) {
+        const uint32_t si = (uint32_t)r * a.t_h;
+#pragma unroll
+        for (int j = 0; j < kCpl; ++j)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) T.v[m][j] = buf_ld_f32(src, vtap[j] + 4u * m, si);
+    };
+    auto emit = [&](const Taps& T, int r) {
+        const uint32_t so = (uint32_t)r * a.d_h;
+#pragma unroll
+        for (int j = 0; j < kCpl; ++j) {
+            const float u = blend<BETA>(T.v[0][j], T.v[1][j], T.v[2][j], T.v[3][j], t[j], s[j], ht[j], hs[j], k[j],
+                                        a.eps4, a.beta, wmask[j]);
+            if constexpr (OUT_U8) buf_st_u8(quant_u8(u * 255.0f), dst, vout[j], so);
+            else buf_st_f32(u, dst, vout[j], so);
+        }
+    };
+    const int r0 = run * kRun, r1 = min(r0 + kRun, a.out_h);
+    Taps A, B;
+    int r = r0;
+    load(A, r);
+    for (; r + 2 <= r1; r += 2) {
+        load(B, r + 1);
+        emit(A, r);
+        load(A, min(r + 2, r1 - 1));
+        emit(B, r + 1);
+    }
+    if (r < r1) emit(A, r);
 }
 
 // bytes of a position table of n entries (256-byte aligned)
@@ -155,40 +287,89 @@ int launch_positions(SamplePos* pos, int n_in, int n_out, hipStream_t st)
     return e == hipSuccess ? WENO_OK : wz_hip_error(e, "positions_kernel launch");
 }
 
-// One pass along `axis` (0: rows, 1: columns); `pos` holds the positions of
-// the resampled axis (dst->h entries for rows, dst->w for columns).
-int launch_resample(int axis, const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, double h,
-                    const SamplePos* pos, hipStream_t st)
+// 4 eps for the kernels' E_s = 4 (eps + SI_s), in the value scale of the pass
+// input (u8: 0..255); beta = 0 takes 1, the weights being C_s whatever eps is
+float eps4_of(const weno_params_t* p, double h, bool u8)
 {
-    ResampleArgs a;
-    const int64_t ei = wz_esize(src->dtype), eo = wz_esize(dst->dtype);
+    const double vs = u8 ? 255.0 : 1.0;
+    return p->beta == 0.0f ? 1.0f : (float)(4.0 * (double)p->k_eps * h * h * vs * vs);
+}
+
+dim3 pass_grid(int chunks, int runs, int planes)
+{
+    const int64_t waves = (int64_t)chunks * runs;
+    return dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock), (unsigned)planes);
+}
+
+// The row pass of src into padded planes at tmp (out_h rows of pitch t_h bytes).
+int launch_rows_pass(const weno_tensor_t* src, uint8_t* tmp, uint32_t t_h, int out_h, const weno_params_t* p,
+                     double h, const SamplePos* pos, hipStream_t st)
+{
+    RowPassArgs a;
+    const int64_t ei = wz_esize(src->dtype);
+    const bool u8 = src->dtype == WENO_U8;
     a.src = (const uint8_t*)src->data;
-    a.dst = (uint8_t*)dst->data;
+    a.tmp = tmp;
+    a.s_n = src->sn * ei;
+    a.s_c = src->sc * ei;
+    a.s_h = (uint32_t)(src->sh * ei);
+    a.s_w = (uint32_t)(src->sw * ei);
+    a.src_extent = (uint32_t)wz_plane_extent(src);
+    a.t_h = t_h;
+    a.t_plane = (uint32_t)((int64_t)out_h * t_h);
     a.C = src->c;
     a.in_h = src->h;
     a.in_w = src->w;
-    a.out_h = dst->h;
-    a.out_w = dst->w;
-    a.s_n = src->sn * ei; a.s_c = src->sc * ei; a.s_h = src->sh * ei; a.s_w = src->sw * ei;
-    a.d_n = dst->sn * eo; a.d_c = dst->sc * eo; a.d_h = dst->sh * eo; a.d_w = dst->sw * eo;
-    a.in_u8 = src->dtype == WENO_U8;
-    a.out_u8 = dst->dtype == WENO_U8;
-    const double vs = a.in_u8 ? 255.0 : 1.0;
-    a.eps = (float)((double)p->k_eps * h * h * vs * vs);
+    a.out_h = out_h;
+    a.chunks = (src->w + kPadCols + 64 * kCpl - 1) / (64 * kCpl);
+    a.runs = (out_h + kRun - 1) / kRun;
+    a.eps4 = eps4_of(p, h, u8);
     a.beta = p->beta;
-    a.out_scale = (float)((a.out_u8 ? 255.0 : 1.0) / vs);
-    dim3 grid((dst->w + 255) / 256, dst->h, dst->n * dst->c);
-    const bool b2 = p->beta == 2.0f;
-    if (axis == 0) {
-        if (b2) launch_typed<0, 2>(a, pos, grid, st);
-        else launch_typed<0, kBetaGeneral>(a, pos, grid, st);
+    const dim3 grid = pass_grid(a.chunks, a.runs, src->n * src->c);
+    if (p->beta == 2.0f) {
+        if (u8) hipLaunchKernelGGL((rows_pass_kernel<2, true>), grid, dim3(kBlock), 0, st, a, pos);
+        else hipLaunchKernelGGL((rows_pass_kernel<2, false>), grid, dim3(kBlock), 0, st, a, pos);
     } else {
-        if (b2) launch_typed<1, 2>(a, pos, grid, st);
-        else launch_typed<1, kBetaGeneral>(a, pos, grid, st);
+        if (u8) hipLaunchKernelGGL((rows_pass_kernel<kBetaGeneral, true>), grid, dim3(kBlock), 0, st, a, pos);
+        else hipLaunchKernelGGL((rows_pass_kernel<kBetaGeneral, false>), grid, dim3(kBlock), 0, st, a, pos);
     }
     const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return wz_hip_error(e, "resample_kernel launch");
-    return WENO_OK;
+    return e == hipSuccess ? WENO_OK : wz_hip_error(e, "rows_pass_kernel launch");
+}
+
+// The column pass of the padded planes at tmp (dst->h rows of pitch t_h) into dst.
+int launch_cols_pass(const uint8_t* tmp, uint32_t t_h, const weno_tensor_t* dst, const weno_params_t* p, double h,
+                     const SamplePos* pos, hipStream_t st)
+{
+    ColPassArgs a;
+    const int64_t eo = wz_esize(dst->dtype);
+    const bool u8 = dst->dtype == WENO_U8;
+    a.tmp = tmp;
+    a.dst = (uint8_t*)dst->data;
+    a.d_n = dst->sn * eo;
+    a.d_c = dst->sc * eo;
+    a.d_h = (uint32_t)(dst->sh * eo);
+    a.d_w = (uint32_t)(dst->sw * eo);
+    a.d_extent = (uint32_t)wz_plane_extent(dst);
+    a.t_h = t_h;
+    a.t_plane = (uint32_t)((int64_t)dst->h * t_h);
+    a.C = dst->c;
+    a.out_h = dst->h;
+    a.out_w = dst->w;
+    a.chunks = (dst->w + 64 * kCpl - 1) / (64 * kCpl);
+    a.runs = (dst->h + kRun - 1) / kRun;
+    a.eps4 = eps4_of(p, h, false);   // the padded planes are float, on the [0,1] scale for u8 inputs
+    a.beta = p->beta;
+    const dim3 grid = pass_grid(a.chunks, a.runs, dst->n * dst->c);
+    if (p->beta == 2.0f) {
+        if (u8) hipLaunchKernelGGL((cols_pass_kernel<2, true>), grid, dim3(kBlock), 0, st, a, pos);
+        else hipLaunchKernelGGL((cols_pass_kernel<2, false>), grid, dim3(kBlock), 0, st, a, pos);
+    } else {
+        if (u8) hipLaunchKernelGGL((cols_pass_kernel<kBetaGeneral, true>), grid, dim3(kBlock), 0, st, a, pos);
+        else hipLaunchKernelGGL((cols_pass_kernel<kBetaGeneral, false>), grid, dim3(kBlock), 0, st, a, pos);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? WENO_OK : wz_hip_error(e, "cols_pass_kernel launch");
 }
 
 // row pitch (floats) of workspace planes: a multiple of 4, so that rows are
@@ -225,7 +406,7 @@ int check_resample_pair(const weno_tensor_t* src, const weno_tensor_t* dst)
     rc = wz_check_tensor(dst);
     if (rc) return rc;
     if (src->n != dst->n || src->c != dst->c) return WENO_EINVAL;
-    if ((int64_t)src->n * src->c > 65535 || dst->h > 65535) return WENO_EINVAL;
+    if ((int64_t)src->n * src->c > 65535) return WENO_EINVAL;
     // offsets within a plane are 32-bit: every plane (and the float
     // intermediate of the row pass) must span less than 2^31 bytes
     if (wz_plane_extent(src) >= (1ll << 31) || wz_plane_extent(dst) >= (1ll << 31)) return WENO_EINVAL;
@@ -235,30 +416,32 @@ int check_resample_pair(const weno_tensor_t* src, const weno_tensor_t* dst)
 
 }  // namespace
 
-// workspace of the resampler: the row pass's float planes (dst->h x src->w),
-// then the position tables of the rows and of the columns
+// workspace of the resampler: the row pass's padded float planes
+// (dst->h x (in_w + 3)), then the position tables of the rows and of the columns
 static size_t resample_bytes(const weno_tensor_t* src, const weno_tensor_t* dst, int64_t in_w)
 {
-    return planes_bytes((int64_t)src->n * src->c, dst->h, in_w) + positions_bytes(dst->h) + positions_bytes(dst->w);
+    return planes_bytes((int64_t)src->n * src->c, dst->h, in_w + kPadCols) + positions_bytes(dst->h) +
+           positions_bytes(dst->w);
 }
 
 // the row pass, then the column pass, of src (any dtype, in_h x in_w) into dst
 static int run_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, double h,
                         uint8_t* ws, hipStream_t st)
 {
-    if ((int64_t)dst->h * f32_pitch(src->w) * 4 >= (1ll << 31)) return WENO_EINVAL;   // 32-bit plane offsets
-    weno_tensor_t tmp = planar_f32(ws, src->n, src->c, dst->h, src->w);
+    const int64_t pitch = f32_pitch((int64_t)src->w + kPadCols);
+    if ((int64_t)dst->h * pitch * 4 >= (1ll << 31)) return WENO_EINVAL;   // 32-bit plane offsets
+    weno_tensor_t tmp = planar_f32(ws, src->n, src->c, dst->h, src->w + kPadCols);
     if (wz_overlap(&tmp, src) || wz_overlap(&tmp, dst)) return WENO_EOVERLAP;
-    uint8_t* tabs = ws + planes_bytes((int64_t)src->n * src->c, dst->h, src->w);
+    uint8_t* tabs = ws + planes_bytes((int64_t)src->n * src->c, dst->h, src->w + kPadCols);
     SamplePos* rows = (SamplePos*)tabs;
     SamplePos* cols = (SamplePos*)(tabs + positions_bytes(dst->h));
     int rc = launch_positions(rows, src->h, dst->h, st);
     if (rc) return rc;
     rc = launch_positions(cols, src->w, dst->w, st);
     if (rc) return rc;
-    rc = launch_resample(0, src, &tmp, p, h, rows, st);
+    rc = launch_rows_pass(src, ws, (uint32_t)(pitch * 4), dst->h, p, h, rows, st);
     if (rc) return rc;
-    return launch_resample(1, &tmp, dst, p, h, cols, st);
+    return launch_cols_pass(ws, (uint32_t)(pitch * 4), dst, p, h, cols, st);
 }
 
 extern "C" size_t weno_resample_workspace(const weno_tensor_t* src, const weno_tensor_t* dst)

@@ -54,6 +54,18 @@ def test_backward_beta(gpu, beta, kind):
     assert _close(got, _ref(V, G, beta=beta))
 
 
+@pytest.mark.parametrize("kind", ["binary", "steps"])
+def test_backward_beta0_without_eps(gpu, kind):
+    # beta = 0, k_eps = 0: constant weights, so the adjoint is the transpose
+    # of a linear map and must stay finite where indicators vanish
+    rng = np.random.default_rng(5)
+    V = random_plane(29, 63, seed=13, kind=kind)
+    G = rng.standard_normal((58, 126))
+    got = gpu.zoom2x_backward(_t(V), _t(G), gpu.Params(beta=0.0, k_eps=0.0)).cpu().numpy()
+    assert np.isfinite(got).all()
+    assert _close(got, _ref(V, G, beta=0.0, keps=0.0))
+
+
 @pytest.mark.parametrize("nbw,h", [(0.125, 1.0), (0.0, 1.0), (-1.0, 0.25)])
 def test_backward_parameters(gpu, nbw, h):
     rng = np.random.default_rng(3)
@@ -159,9 +171,9 @@ def test_inverse_problem_recovers_input(gpu):
         loss.backward()
         opt.step()
         if first is None:
-            first = float(loss)
-    assert float(loss) < 1e-3 * first
-    assert float((x - xs).abs().max()) < 0.05
+            first = float(loss.detach())
+    assert float(loss.detach()) < 1e-3 * first
+    assert float((x.detach() - xs).abs().max()) < 0.05
 
 
 def _fit(gpu, target, shape, steps=200, lr=1e-2):
@@ -173,7 +185,7 @@ def _fit(gpu, target, shape, steps=200, lr=1e-2):
         loss = torch.mean((gpu.WenoZoom2x.apply(x) - target) ** 2)
         loss.backward()
         opt.step()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
     return x.detach(), losses
 
 

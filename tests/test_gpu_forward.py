@@ -52,6 +52,18 @@ def test_forward_beta(gpu, beta, kind):
     assert np.abs(U - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("kind", ["binary", "steps"])
+def test_forward_beta0_without_eps(gpu, kind):
+    # beta = 0 allows k_eps = 0; flat regions then have zero indicators and
+    # the weights must still be the constant 0.5 / t^0 (0^0 = 1), not NaN
+    _set(gpu, (64, 2))
+    V = random_plane(37, 90, seed=21, kind=kind).astype(np.float32)
+    U = gpu.zoom2x(_f32(V), beta=0.0, k_eps=0.0).cpu().numpy()
+    ref = oracle.zoom2x(V.astype(np.float64), beta=0.0, keps=0.0)
+    assert np.isfinite(U).all()
+    assert np.abs(U - ref).max() <= TOL
+
+
 @pytest.mark.parametrize("nbw,h,keps", [(0.125, 1.0, 1e-8), (0.0, 1.0, 1e-8), (-1.0, 0.5, 1e-6), (-1.0, 2.0, 1e-8)])
 def test_forward_parameters(gpu, nbw, h, keps):
     _set(gpu, (64, 2))

@@ -93,3 +93,47 @@ def test_zoom_to_odd_widths_two_levels(gpu, shape, out):
     got = gpu.zoom_to(_t(V), *out).cpu().numpy()
     ref = R.zoom_to(V.astype(np.float32).astype(np.float64), *out)
     assert np.abs(got - ref).max() <= 3 * TOL
+
+
+@pytest.mark.parametrize("op", ["resample", "zoom_to"])
+def test_beta0_without_eps(gpu, op):
+    # beta = 0 allows k_eps = 0: the weights are the ideal C_0, C_1 even where
+    # both indicators vanish (flat regions), never 0/0
+    V = random_plane(31, 47, seed=23, kind="binary").astype(np.float32)
+    p = gpu.Params(beta=0.0, k_eps=0.0)
+    if op == "resample":
+        got = gpu.resample(_t(V), 45, 70, p).cpu().numpy()
+        ref = R.tensor_resample(V.astype(np.float64), 45, 70, beta=0.0, keps=0.0)
+    else:
+        got = gpu.zoom_to(_t(V), 100, 151, p).cpu().numpy()
+        ref = R.zoom_to(V.astype(np.float64), 100, 151, beta=0.0, keps=0.0)
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= 3 * TOL
+
+
+@pytest.mark.parametrize("shape,out", [((300, 700), (517, 1201)), ((517, 1201), (300, 700)), ((257, 1031), (96, 97))])
+def test_resample_many_tiles(gpu, shape, out):
+    # several column chunks and row runs per plane, ragged at both ends,
+    # upsampling and downsampling (the last ~10.7x in width), 3 planes
+    V = np.stack([random_plane(*shape, seed=30 + c, kind="steps") * 0.6 + 0.4 * random_plane(*shape, seed=40 + c)
+                  for c in range(3)]).astype(np.float32)
+    got = gpu.resample(_t(V), *out).cpu().numpy()
+    ref = R.tensor_resample(V.astype(np.float64), *out)
+    assert np.abs(got - ref).max() <= TOL
+
+
+def test_resample_u8_hwc_many_tiles(gpu):
+    img = scene_rgb(211, 640, seed=12, n_polygons=12)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    y = gpu.resample(x, 300, 913)
+    ref = R.tensor_resample(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 300, 913)
+    ties, errors = u8_compare(y.cpu().numpy(), ref)
+    assert errors == 0
+
+
+def test_resample_nodes_are_copies(gpu):
+    # an output grid of 2n - 1 samples puts every other sample on an input
+    # node: those are the input values bit for bit
+    V = random_plane(123, 301, seed=9, kind="uniform").astype(np.float32)
+    got = gpu.resample(_t(V), 245, 601).cpu().numpy()
+    assert np.array_equal(got[::2, ::2], V)
