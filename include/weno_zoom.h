@@ -154,8 +154,9 @@ int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t* dst, int3
  * copied exactly; samples beyond the ends are clamped.  eps = k_eps h^2 as for
  * the doubling (nbw is unused).
  *   d_workspace: DEVICE memory of at least weno_resample_workspace(src, dst)
- *                bytes (an FP32 (n, c, H, w + 3) intermediate, edge columns
- *                replicated, and the positions of the H rows and W columns).
+ *                bytes: the positions of the H rows and W columns and, only
+ *                where (w - 1)/(W - 1) exceeds about 16, an FP32
+ *                (n, c, H, w + 3) intermediate.  Kernels only: capturable.
  */
 size_t weno_resample_workspace(const weno_tensor_t* src, const weno_tensor_t* dst);
 int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, void* d_workspace,

@@ -73,10 +73,8 @@ struct SamplePos {
 // Positions j (n_in - 1)/(n_out - 1) = i + t of an axis, one thread each,
 // worked out in integers so that nodes are exact; t and k are rounded once
 // from exact ratios.
-__global__ __launch_bounds__(256) void positions_kernel(SamplePos* __restrict__ pos, int n_in, int n_out)
+__device__ void sample_position(SamplePos* __restrict__ pos, int j, int n_in, int n_out)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_out) return;
     SamplePos p;
     p.i = 0;
     p.t = 0.0f;
@@ -100,6 +98,15 @@ __global__ __launch_bounds__(256) void positions_kernel(SamplePos* __restrict__ 
         }
     }
     pos[j] = p;
+}
+
+// both tables in one launch: rows first, then columns
+__global__ __launch_bounds__(256) void positions_kernel(SamplePos* __restrict__ rows, int h_in, int h_out,
+                                                        SamplePos* __restrict__ cols, int w_in, int w_out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < h_out) sample_position(rows, j, h_in, h_out);
+    else if (j - h_out < w_out) sample_position(cols, j - h_out, w_in, w_out);
 }
 
 // Work split of both passes: a wave owns kCpl columns per lane (64 apart, so
@@ -277,12 +284,130 @@ __global__ __launch_bounds__(256) void cols_pass_kernel(ColPassArgs a, const Sam
     if (r < r1) emit(A, r);
 }
 
+// Fused tensor resampler: a block of 256 threads owns a tile of `tw` output
+// columns and a run of output rows of one plane.  For each output row it
+// first resamples the four input rows of that row's interval at the input
+// columns its columns' intervals touch (columns xa .. xa + 256 M - 1, xa =
+// i(c0) - 1, clamped), into an LDS row, then resamples that row along the
+// columns; the float intermediate of the two-pass form never leaves the CU.
+// The arithmetic, operands and their order are those of the two passes, so
+// both forms give the same bits.  The host picks M and tw so that a tile's
+// span i(c_last) - i(c0) + 4 fits in 256 M samples.
+constexpr int kFuseQ = 3;          // output columns per thread at most (tw <= 768)
+constexpr int kFuseMaxTw = 256 * kFuseQ;
+
+struct FusedArgs {
+    const uint8_t* src;
+    uint8_t* dst;
+    int64_t s_n, s_c, d_n, d_c;
+    uint32_t s_h, s_w, d_h, d_w;
+    uint32_t src_extent, d_extent;
+    int32_t C, in_h, in_w, out_h, out_w;
+    int32_t tw, ctiles, run;          // tile width, tiles per row, rows per run
+    float eps4_in, eps4, beta;        // eps4_in in the input's value scale, eps4 on the float scale
+};
+
+template <int BETA, int M, bool IN_U8, bool OUT_U8>
+__global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const SamplePos* __restrict__ prow,
+                                                             const SamplePos* __restrict__ pcol)
+{
+    __shared__ float row_buf[2][256 * M];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tile = blockIdx.x;
+    const int rr = tile / a.ctiles, ct = tile - rr * a.ctiles;
+    const int plane = blockIdx.y;
+    const int n = plane / a.C, ch = plane - n * a.C;
+    const rsrc_t src = make_rsrc(a.src + n * a.s_n + ch * a.s_c, a.src_extent);
+    const rsrc_t dst = make_rsrc(a.dst + n * a.d_n + ch * a.d_c, a.d_extent);
+    const int c0 = ct * a.tw, c1 = min(c0 + a.tw, a.out_w);
+    const int xa = pcol[c0].i - 1;
+    // row phase: the input columns of this thread's LDS slots
+    uint32_t vin[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) vin[m] = (uint32_t)min(max(xa + tid + 256 * m, 0), a.in_w - 1) * a.s_w;
+    // column phase: per output column, the LDS index of its first tap and its weights
+    int lb[kFuseQ];
+    uint32_t vout[kFuseQ];
+    float t[kFuseQ], s[kFuseQ], ht[kFuseQ], hs[kFuseQ], k[kFuseQ], wmask[kFuseQ];
+    bool live[kFuseQ];   // uniform: the wave owns a column of this slot
+#pragma unroll
+    for (int q = 0; q < kFuseQ; ++q) {
+        const int c = c0 + tid + 256 * q;
+        live[q] = c0 + 256 * q + 64 * wave < c1;
+        const SamplePos p = pcol[min(c, a.out_w - 1)];
+        lb[q] = p.i - 1 - xa;
+        vout[q] = c < c1 ? (uint32_t)c * a.d_w : kOob;
+        t[q] = p.t;
+        s[q] = p.t - 1.0f;
+        ht[q] = 0.5f * t[q];
+        hs[q] = 0.5f * s[q];
+        k[q] = p.k;
+        wmask[q] = p.node ? 0.0f : 1.0f;
+    }
+    constexpr float kScale = IN_U8 ? 1.0f / 255.0f : 1.0f;
+    using raw = typename std::conditional<IN_U8, uint8_t, float>::type;
+    auto ld = [&](uint32_t voff, uint32_t soff) -> raw {
+        if constexpr (IN_U8) return __builtin_amdgcn_raw_buffer_load_b8(src, (int)voff, (int)soff, 0);
+        else return buf_ld_f32(src, voff, soff);
+    };
+    raw A[M][4];
+    float At = 0.0f, Ak = 0.0f;
+    auto load = [&](int r) {
+        const SamplePos p = prow[r];
+        const uint32_t s0 = (uint32_t)p.i * a.s_h;
+        const bool node = p.node != 0;   // four taps on the node's row: the blend returns it exactly
+        const uint32_t sm = node ? s0 : (uint32_t)max(p.i - 1, 0) * a.s_h;
+        const uint32_t s1 = node ? s0 : s0 + a.s_h;
+        const uint32_t s2 = node ? s0 : (uint32_t)min(p.i + 2, a.in_h - 1) * a.s_h;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            A[m][0] = ld(vin[m], sm);
+            A[m][1] = ld(vin[m], s0);
+            A[m][2] = ld(vin[m], s1);
+            A[m][3] = ld(vin[m], s2);
+        }
+        At = p.t;
+        Ak = p.k;
+    };
+    const int r0 = rr * a.run, r1 = min(r0 + a.run, a.out_h);
+    auto step = [&](int r, float* buf) {
+        {
+            const float tt = At, ss = tt - 1.0f, htt = 0.5f * tt, hss = 0.5f * ss;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                buf[tid + 256 * m] = blend<BETA>((float)A[m][0], (float)A[m][1], (float)A[m][2], (float)A[m][3], tt, ss,
+                                                 htt, hss, Ak, a.eps4_in, a.beta) *
+                                     kScale;
+        }
+        __syncthreads();
+        load(min(r + 1, r1 - 1));
+        const uint32_t so = (uint32_t)r * a.d_h;
+#pragma unroll
+        for (int q = 0; q < kFuseQ; ++q) {
+            if (!live[q]) continue;
+            const float* L = buf + lb[q];
+            const float u = blend<BETA>(L[0], L[1], L[2], L[3], t[q], s[q], ht[q], hs[q], k[q], a.eps4, a.beta, wmask[q]);
+            if constexpr (OUT_U8) buf_st_u8(quant_u8(u * 255.0f), dst, vout[q], so);
+            else buf_st_f32(u, dst, vout[q], so);
+        }
+    };
+    load(r0);
+    int r = r0;
+    for (; r + 2 <= r1; r += 2) {
+        step(r, row_buf[0]);
+        step(r + 1, row_buf[1]);
+    }
+    if (r < r1) step(r, row_buf[0]);
+}
+
 // bytes of a position table of n entries (256-byte aligned)
 size_t positions_bytes(int64_t n) { return (size_t)((n * (int64_t)sizeof(SamplePos) + 255) / 256 * 256); }
 
-int launch_positions(SamplePos* pos, int n_in, int n_out, hipStream_t st)
+int launch_positions(SamplePos* rows, int h_in, int h_out, SamplePos* cols, int w_in, int w_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(positions_kernel, dim3((n_out + 255) / 256), dim3(256), 0, st, pos, n_in, n_out);
+    hipLaunchKernelGGL(positions_kernel, dim3((h_out + w_out + 255) / 256), dim3(256), 0, st, rows, h_in, h_out, cols,
+                       w_in, w_out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? WENO_OK : wz_hip_error(e, "positions_kernel launch");
 }
@@ -372,6 +497,107 @@ int launch_cols_pass(const uint8_t* tmp, uint32_t t_h, const weno_tensor_t* dst,
     return e == hipSuccess ? WENO_OK : wz_hip_error(e, "cols_pass_kernel launch");
 }
 
+// Launch shape of the fused resampler along a row of n_in -> n_out samples:
+// 256 M LDS slots per row and a tile width tw <= 768 whose span fits them,
+// ceil((tw - 1)(n_in - 1)/(n_out - 1)) + 4 <= 256 M, with the row's tiles
+// balanced.  M = 2 is taken wherever it allows tiles of 64 columns (width
+// ratios up to ~7.9): it measured fastest from upsampling by 1.5 to
+// downsampling by 1.9, against M = 1 (more tiles, each paying a barrier and
+// its pipeline fill per row) and M = 4 (twice the tap registers).  Larger
+// ratios take M = 3 or 4; beyond ~16, ok = false and the two passes run.
+struct FusedShape {
+    bool ok;
+    int m, tw, ctiles;
+};
+
+FusedShape fused_shape(int n_in, int n_out)
+{
+    const int64_t num = n_in > 1 ? n_in - 1 : 0, den = n_out > 1 ? n_out - 1 : 1;
+    const int64_t min_tw = n_out < 64 ? n_out : 64;
+    for (int m = 2; m <= 4; ++m) {
+        int64_t twmax = num == 0 ? kFuseMaxTw : (256ll * m - 4) * den / num + 1;
+        if (twmax > kFuseMaxTw) twmax = kFuseMaxTw;
+        if (twmax < min_tw) continue;
+        const int64_t tiles = (n_out + twmax - 1) / twmax;
+        return {true, m, (int)((n_out + tiles - 1) / tiles), (int)tiles};
+    }
+    return {false, 0, 0, 0};
+}
+
+// rows per run of the fused resampler: 8 for small launches, up to 32 once
+// there are more than 16 runs' worth of tile rows per compute unit
+int fused_run(int out_h, int ctiles, int64_t planes)
+{
+    const int64_t tile_rows = (int64_t)out_h * ctiles * planes;
+    int64_t run = tile_rows / (256 * 16);
+    if (run < 8) run = 8;
+    if (run > 32) run = 32;
+    return (int)run;
+}
+
+template <int BETA, int M>
+void launch_fused_typed(const FusedArgs& a, bool in_u8, bool out_u8, dim3 grid, const SamplePos* prow,
+                        const SamplePos* pcol, hipStream_t st)
+{
+    if (in_u8 && out_u8)
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, true, true>), grid, dim3(256), 0, st, a, prow, pcol);
+    else if (in_u8)
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, true, false>), grid, dim3(256), 0, st, a, prow, pcol);
+    else if (out_u8)
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, false, true>), grid, dim3(256), 0, st, a, prow, pcol);
+    else
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, false, false>), grid, dim3(256), 0, st, a, prow, pcol);
+}
+
+template <int BETA>
+void launch_fused_beta(const FusedArgs& a, int m, bool in_u8, bool out_u8, dim3 grid, const SamplePos* prow,
+                       const SamplePos* pcol, hipStream_t st)
+{
+    switch (m) {
+    case 2: launch_fused_typed<BETA, 2>(a, in_u8, out_u8, grid, prow, pcol, st); break;
+    case 3: launch_fused_typed<BETA, 3>(a, in_u8, out_u8, grid, prow, pcol, st); break;
+    default: launch_fused_typed<BETA, 4>(a, in_u8, out_u8, grid, prow, pcol, st); break;
+    }
+}
+
+int launch_fused(const weno_tensor_t* src, const weno_tensor_t* dst, const FusedShape& fs, const weno_params_t* p,
+                 double h, const SamplePos* prow, const SamplePos* pcol, hipStream_t st)
+{
+    FusedArgs a;
+    const int64_t ei = wz_esize(src->dtype), eo = wz_esize(dst->dtype);
+    const bool in_u8 = src->dtype == WENO_U8, out_u8 = dst->dtype == WENO_U8;
+    a.src = (const uint8_t*)src->data;
+    a.dst = (uint8_t*)dst->data;
+    a.s_n = src->sn * ei;
+    a.s_c = src->sc * ei;
+    a.d_n = dst->sn * eo;
+    a.d_c = dst->sc * eo;
+    a.s_h = (uint32_t)(src->sh * ei);
+    a.s_w = (uint32_t)(src->sw * ei);
+    a.d_h = (uint32_t)(dst->sh * eo);
+    a.d_w = (uint32_t)(dst->sw * eo);
+    a.src_extent = (uint32_t)wz_plane_extent(src);
+    a.d_extent = (uint32_t)wz_plane_extent(dst);
+    a.C = src->c;
+    a.in_h = src->h;
+    a.in_w = src->w;
+    a.out_h = dst->h;
+    a.out_w = dst->w;
+    a.tw = fs.tw;
+    a.ctiles = fs.ctiles;
+    const int64_t planes = (int64_t)src->n * src->c;
+    a.run = fused_run(dst->h, fs.ctiles, planes);
+    a.eps4_in = eps4_of(p, h, in_u8);
+    a.eps4 = eps4_of(p, h, false);
+    a.beta = p->beta;
+    const int64_t runs = (dst->h + a.run - 1) / a.run;
+    const dim3 grid((unsigned)(runs * fs.ctiles), (unsigned)planes);
+    if (p->beta == 2.0f) launch_fused_beta<2>(a, fs.m, in_u8, out_u8, grid, prow, pcol, st);
+    else launch_fused_beta<kBetaGeneral>(a, fs.m, in_u8, out_u8, grid, prow, pcol, st);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? WENO_OK : wz_hip_error(e, "fused_resample_kernel launch");
+}
+
 // row pitch (floats) of workspace planes: a multiple of 4, so that rows are
 // 16-byte aligned and the forward kernel stores them with vector stores
 int64_t f32_pitch(int64_t w) { return (w + 3) / 4 * 4; }
@@ -416,32 +642,39 @@ int check_resample_pair(const weno_tensor_t* src, const weno_tensor_t* dst)
 
 }  // namespace
 
-// workspace of the resampler: the row pass's padded float planes
-// (dst->h x (in_w + 3)), then the position tables of the rows and of the columns
+// workspace of the resampler: the position tables of the rows and of the
+// columns, then (only where the fused kernel does not apply) the row pass's
+// padded float planes (dst->h x (in_w + 3))
 static size_t resample_bytes(const weno_tensor_t* src, const weno_tensor_t* dst, int64_t in_w)
 {
-    return planes_bytes((int64_t)src->n * src->c, dst->h, in_w + kPadCols) + positions_bytes(dst->h) +
-           positions_bytes(dst->w);
+    const size_t tabs = positions_bytes(dst->h) + positions_bytes(dst->w);
+    if (fused_shape((int)in_w, dst->w).ok) return tabs;
+    return tabs + planes_bytes((int64_t)src->n * src->c, dst->h, in_w + kPadCols);
 }
 
-// the row pass, then the column pass, of src (any dtype, in_h x in_w) into dst
+// src (any dtype, in_h x in_w) resampled into dst: the fused kernel, or the
+// row pass then the column pass
 static int run_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, double h,
                         uint8_t* ws, hipStream_t st)
 {
+    SamplePos* rows = (SamplePos*)ws;
+    SamplePos* cols = (SamplePos*)(ws + positions_bytes(dst->h));
+    uint8_t* tmp = ws + positions_bytes(dst->h) + positions_bytes(dst->w);
+    const FusedShape fs = fused_shape(src->w, dst->w);
+    if (fs.ok) {
+        int rc = launch_positions(rows, src->h, dst->h, cols, src->w, dst->w, st);
+        if (rc) return rc;
+        return launch_fused(src, dst, fs, p, h, rows, cols, st);
+    }
     const int64_t pitch = f32_pitch((int64_t)src->w + kPadCols);
     if ((int64_t)dst->h * pitch * 4 >= (1ll << 31)) return WENO_EINVAL;   // 32-bit plane offsets
-    weno_tensor_t tmp = planar_f32(ws, src->n, src->c, dst->h, src->w + kPadCols);
-    if (wz_overlap(&tmp, src) || wz_overlap(&tmp, dst)) return WENO_EOVERLAP;
-    uint8_t* tabs = ws + planes_bytes((int64_t)src->n * src->c, dst->h, src->w + kPadCols);
-    SamplePos* rows = (SamplePos*)tabs;
-    SamplePos* cols = (SamplePos*)(tabs + positions_bytes(dst->h));
-    int rc = launch_positions(rows, src->h, dst->h, st);
+    weno_tensor_t t = planar_f32(tmp, src->n, src->c, dst->h, src->w + kPadCols);
+    if (wz_overlap(&t, src) || wz_overlap(&t, dst)) return WENO_EOVERLAP;
+    int rc = launch_positions(rows, src->h, dst->h, cols, src->w, dst->w, st);
     if (rc) return rc;
-    rc = launch_positions(cols, src->w, dst->w, st);
+    rc = launch_rows_pass(src, tmp, (uint32_t)(pitch * 4), dst->h, p, h, rows, st);
     if (rc) return rc;
-    rc = launch_rows_pass(src, ws, (uint32_t)(pitch * 4), dst->h, p, h, rows, st);
-    if (rc) return rc;
-    return launch_cols_pass(ws, (uint32_t)(pitch * 4), dst, p, h, cols, st);
+    return launch_cols_pass(tmp, (uint32_t)(pitch * 4), dst, p, h, cols, st);
 }
 
 extern "C" size_t weno_resample_workspace(const weno_tensor_t* src, const weno_tensor_t* dst)

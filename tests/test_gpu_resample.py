@@ -111,10 +111,12 @@ def test_beta0_without_eps(gpu, op):
     assert np.abs(got - ref).max() <= 3 * TOL
 
 
-@pytest.mark.parametrize("shape,out", [((300, 700), (517, 1201)), ((517, 1201), (300, 700)), ((257, 1031), (96, 97))])
+# width ratios 0.58, 1.7, 2.3 (LDS rows of 512 samples per tile), 10.7 (768),
+# 14 (1024) and 20.2 (beyond the fused kernel: row pass, then column pass)
+@pytest.mark.parametrize("shape,out", [((300, 700), (517, 1201)), ((517, 1201), (300, 700)), ((97, 3001), (40, 1291)),
+                                       ((257, 1031), (96, 97)), ((40, 1400), (20, 101)), ((20, 2000), (10, 100))])
 def test_resample_many_tiles(gpu, shape, out):
-    # several column chunks and row runs per plane, ragged at both ends,
-    # upsampling and downsampling (the last ~10.7x in width), 3 planes
+    # several column tiles and row runs per plane, ragged at both ends, 3 planes
     V = np.stack([random_plane(*shape, seed=30 + c, kind="steps") * 0.6 + 0.4 * random_plane(*shape, seed=40 + c)
                   for c in range(3)]).astype(np.float32)
     got = gpu.resample(_t(V), *out).cpu().numpy()
