@@ -9,10 +9,11 @@ inputs resident in HBM.
 
 Extra fields (same line): the uint8 HWC variant of the frame, 512 uneven
 images in one persistent launch vs a per-image launch loop, three fused
-doublings of a 256x256 pixel-art image replayed from a HIP graph, and
+doublings of a 256x256 pixel-art image replayed from a HIP graph, zooming the
+frame to 5760x3240 (two doublings and the tensor resampler), and
 forward+backward of a 16x3x512x512 float32 batch.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main | --only-zoom-to]
 """
 from __future__ import annotations
 
@@ -107,6 +108,36 @@ def cpu_baseline(img_planar, budget_s=10.0):
     }
 
 
+def copy_calibration(torch, dev):
+    """Three plain 256 MiB device copies: the reference for the HBM byte counters."""
+    a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x %d bytes read + written" % (a.numel() * 4))
+
+
+def zoom_to_extra(wz, torch, x, dev, steps):
+    """Zoom to any size, 1080p RGB f32 -> 5760x3240 (scale 3): two doublings
+    to the nested 7679x4319 grid, then the tensor resampler (Section 3.3);
+    the resampler alone is also timed on a grid of that size."""
+    H, W = x.shape[-2:]
+    OH3, OW3 = 3 * H, 3 * W
+    ws_zt = torch.empty(wz.zoom_to_workspace_bytes(x, OH3, OW3), dtype=torch.uint8, device=dev)
+    ms_zt = timed(lambda: wz.zoom_to(x, OH3, OW3, workspace=ws_zt), steps, 20, torch)
+    xg = torch.rand((3, 4 * (H - 1) + 1, 4 * (W - 1) + 1), device=dev)
+    ws_rs = torch.empty(max(1, wz.resample_workspace_bytes(xg, OH3, OW3)), dtype=torch.uint8, device=dev)
+    ms_rs = timed(lambda: wz.resample(xg, OH3, OW3, workspace=ws_rs), steps, 20, torch)
+    rs_bytes = 4 * (xg.numel() + 3 * OH3 * OW3)
+    log("zoom_to 1080p -> 5760x3240: %.4f ms (resample stage %.4f ms)" % (ms_zt, ms_rs))
+    return {"ms": round(ms_zt, 4), "Mpix_per_s": round(OH3 * OW3 / (ms_zt * 1e-3) / 1e6, 1),
+            "resample_stage_ms": round(ms_rs, 4),
+            "resample_stage_GBps_algorithmic": round(rs_bytes / (ms_rs * 1e-3) / 1e9, 1),
+            "resample_stage_hbm_frac": round(rs_bytes / (ms_rs * 1e-3) / 8e12, 3),
+            "resample_stage_algorithmic_bytes": rs_bytes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +147,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=3000)
     ap.add_argument("--only-main", action="store_true", help="time only the headline kernel (for profilers)")
+    ap.add_argument("--only-zoom-to", action="store_true",
+                    help="time only zoom_to 1080p -> 5760x3240 and its resampler (for profilers)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
@@ -140,6 +173,11 @@ def main():
     planar = to_planar_f32(img)
     x = torch.tensor(planar, device=dev)
     y = torch.empty((3, 2 * H, 2 * W), dtype=torch.float32, device=dev)
+    if args.only_zoom_to:
+        if args.copy_calib:
+            copy_calibration(torch, dev)
+        print(json.dumps(zoom_to_extra(wz, torch, x, dev, args.steps)), flush=True)
+        return
     log("headline: zoom2x RGB fp32 %dx%d, steps %d warmup %d" % (W, H, args.steps, args.warmup))
     ms = timed(lambda: wz.zoom2x_(x, y), args.steps, args.warmup, torch)
     out_px = 4 * H * W
@@ -185,12 +223,7 @@ def main():
         },
     }
     if args.copy_calib:
-        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy calibration: 3 x %d bytes read + written" % (a.numel() * 4))
+        copy_calibration(torch, dev)
     if args.only_main:
         print(json.dumps(result), flush=True)
         return
@@ -303,6 +336,8 @@ def main():
                                    "Mpix_per_s_graph": round(2048 * 2048 / (ms_g * 1e-3) / 1e6, 1)}
     log("cascade: graph %.4f ms eager %.4f ms" % (ms_g, ms_e))
     del res
+
+    extras["zoom_to_rgb_f32_1080p_to_5760x3240"] = zoom_to_extra(wz, torch, x, dev, max(20, args.steps // 10))
 
     # ---------------- forward + backward, 16 x 3 x 512 x 512 ----------------
     try:

@@ -30,6 +30,8 @@ __all__ = [
     "zoom2x_backward",
     "resample",
     "zoom_to",
+    "resample_workspace_bytes",
+    "zoom_to_workspace_bytes",
     "WenoZoom2x",
     "set_launch_config",
     "get_launch_config",
@@ -216,6 +218,22 @@ def resample(x: torch.Tensor, out_h: int, out_w: int, params: Params | None = No
     out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
     L = _lib.lib()
     return _ws_call(L.weno_resample_workspace, L.weno_resample, "weno_resample", x, out, params, workspace)
+
+
+def _ws_bytes(fn_ws, x, out_h, out_w, out_dtype):
+    s = _desc(x)
+    d = WenoTensor(1, _DT[out_dtype or x.dtype], *_as4d(x).shape[:2], int(out_h), int(out_w), 0, 0, 0, 0)
+    return int(fn_ws(ctypes.byref(s), ctypes.byref(d)))
+
+
+def resample_workspace_bytes(x: torch.Tensor, out_h: int, out_w: int, out_dtype=None) -> int:
+    """Workspace `resample` needs for x -> (out_h, out_w) (0: invalid sizes)."""
+    return _ws_bytes(_lib.lib().weno_resample_workspace, x, out_h, out_w, out_dtype)
+
+
+def zoom_to_workspace_bytes(x: torch.Tensor, out_h: int, out_w: int, out_dtype=None) -> int:
+    """Workspace `zoom_to` needs for x -> (out_h, out_w) (0: invalid sizes)."""
+    return _ws_bytes(_lib.lib().weno_zoom_to_workspace, x, out_h, out_w, out_dtype)
 
 
 def zoom_to(x: torch.Tensor, out_h: int, out_w: int, params: Params | None = None, out_dtype=None,

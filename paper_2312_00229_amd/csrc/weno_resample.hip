@@ -330,11 +330,11 @@ __global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const 
     int lb[kFuseQ];
     uint32_t vout[kFuseQ];
     float t[kFuseQ], s[kFuseQ], ht[kFuseQ], hs[kFuseQ], k[kFuseQ], wmask[kFuseQ];
-    bool live[kFuseQ];   // uniform: the wave owns a column of this slot
+    int live = 0;   // bit q: the wave owns a column of slot q (uniform)
 #pragma unroll
     for (int q = 0; q < kFuseQ; ++q) {
         const int c = c0 + tid + 256 * q;
-        live[q] = c0 + 256 * q + 64 * wave < c1;
+        live |= (c0 + 256 * q + 64 * wave < c1) << q;
         const SamplePos p = pcol[min(c, a.out_w - 1)];
         lb[q] = p.i - 1 - xa;
         vout[q] = c < c1 ? (uint32_t)c * a.d_w : kOob;
@@ -345,6 +345,7 @@ __global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const 
         k[q] = p.k;
         wmask[q] = p.node ? 0.0f : 1.0f;
     }
+    live = __builtin_amdgcn_readfirstlane(live);
     constexpr float kScale = IN_U8 ? 1.0f / 255.0f : 1.0f;
     using raw = typename std::conditional<IN_U8, uint8_t, float>::type;
     auto ld = [&](uint32_t voff, uint32_t soff) -> raw {
@@ -382,10 +383,11 @@ __global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const 
         }
         __syncthreads();
         load(min(r + 1, r1 - 1));
-        const uint32_t so = (uint32_t)r * a.d_h;
+        // uniform (kept in a scalar register: a buffer store's row offset)
+        const uint32_t so = __builtin_amdgcn_readfirstlane((uint32_t)r * a.d_h);
 #pragma unroll
         for (int q = 0; q < kFuseQ; ++q) {
-            if (!live[q]) continue;
+            if (!((live >> q) & 1)) continue;
             const float* L = buf + lb[q];
             const float u = blend<BETA>(L[0], L[1], L[2], L[3], t[q], s[q], ht[q], hs[q], k[q], a.eps4, a.beta, wmask[q]);
             if constexpr (OUT_U8) buf_st_u8(quant_u8(u * 255.0f), dst, vout[q], so);
