@@ -108,6 +108,55 @@ def cpu_baseline(img_planar, budget_s=10.0):
     }
 
 
+def cpu_baseline_others(batch_imgs):
+    """Bounded samples of the other workloads on the FP64 oracle, and the
+    headline frame's first plane on one thread (a few seconds in total)."""
+    import ctypes
+
+    import oracle
+    from workloads import pixel_art, scene_rgb, to_planar_f32
+
+    out = {}
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    plane = to_planar_f32(scene_rgb(1080, 1920, seed=0))[0].astype(np.float64)
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        oracle.zoom2x(plane)
+        dt = time.perf_counter() - t0
+        gomp.omp_set_num_threads(cores)
+        out["one_core_1080p"] = {"value": round(4 * plane.size / dt / 1e6, 3), "unit": "output Mpix/s (one plane)",
+                                 "cores": 1, "seconds": round(dt, 3)}
+    except OSError as e:
+        out["one_core_1080p"] = {"error": str(e)}
+    pa = pixel_art(256, 256, seed=1).transpose(2, 0, 1).astype(np.float64) / 255.0
+    t0 = time.perf_counter()
+    oracle.cascade(pa, 3)
+    dt = time.perf_counter() - t0
+    out["cascade_256_x8"] = {"value": round(2048 * 2048 / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
+                             "seconds": round(dt, 3), "sample": "the whole workload (3 levels, FP64 intermediates)"}
+    sample = batch_imgs[:16]
+    t0 = time.perf_counter()
+    for im in sample:
+        oracle.zoom2x(np.transpose(im, (2, 0, 1)).astype(np.float64) / 255.0)
+    dt = time.perf_counter() - t0
+    opx = sum(4 * im.shape[0] * im.shape[1] for im in sample)
+    out["batched_16_of_512"] = {"value": round(opx / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
+                                "seconds": round(dt, 3), "sample": "the first 16 images of the 512"}
+    x = to_planar_f32(scene_rgb(512, 512, seed=100, n_polygons=20)).astype(np.float64)
+    g = np.random.default_rng(0).standard_normal((3, 1024, 1024))
+    t0 = time.perf_counter()
+    oracle.zoom2x(x)
+    for c in range(3):
+        oracle.backward(x[c], g[c])
+    dt = time.perf_counter() - t0
+    out["fwd_bwd_1_of_16x3x512"] = {"value": round(1024 * 1024 / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
+                                    "seconds": round(dt, 3),
+                                    "sample": "one 3x512x512 image of the 16 (forward: OpenMP; hand adjoint: serial)"}
+    return out
+
+
 def copy_calibration(torch, dev):
     """Three plain 256 MiB device copies: the reference for the HBM byte counters."""
     a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -367,6 +416,7 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle) ...")
         result["cpu_baseline"] = cpu_baseline(planar)
+        result["cpu_baseline"]["others"] = cpu_baseline_others(imgs)
     print(json.dumps(result), flush=True)
 
 

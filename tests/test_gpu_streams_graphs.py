@@ -79,6 +79,25 @@ def test_backward_graph_replay(gpu):
         assert torch.equal(res, eager), k
 
 
+@pytest.mark.parametrize("op,shape,out", [("zoom_to", (45, 70), (130, 201)),     # doublings + fused resampler
+                                          ("resample", (30, 1500), (17, 70))])  # the two-pass resampler
+def test_zoom_to_and_resample_graph_replay(gpu, op, shape, out):
+    x = torch.tensor(random_plane(*shape, seed=8, kind="steps").astype(np.float32), device="cuda")
+    fn = gpu.zoom_to if op == "zoom_to" else gpu.resample
+    size = gpu.zoom_to_workspace_bytes if op == "zoom_to" else gpu.resample_workspace_bytes
+    ws = torch.empty(size(x, *out), dtype=torch.uint8, device="cuda")
+    eager = fn(x, *out, workspace=ws)
+    g, res = _capture(lambda: fn(x, *out, workspace=ws))
+    for k in range(4):
+        res.fill_(float("nan"))
+        ws.fill_(255)                          # stale workspace contents must not matter
+        _ = fn(x * 0.5, *out)                  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(res, eager), k
+
+
 def test_calls_on_a_side_stream(gpu):
     gpu.set_launch_config(0, 0)
     x = torch.tensor(random_plane(100, 200, seed=9, kind="uniform").astype(np.float32), device="cuda")
