@@ -59,6 +59,19 @@ extern "C" {
 
 typedef enum { WENO_U8 = 0, WENO_F32 = 1 } weno_dtype_t;
 
+/* Input samples outside an (h, w) plane, read by quads near its edges. */
+typedef enum {
+    WENO_BOUNDARY_CLAMP = 0,    /* the nearest edge sample (default)                   */
+    WENO_BOUNDARY_EXTERNAL = 1  /* the caller's own data: rows -4 .. h+4 and columns
+                                   -4 .. w+4 of every plane, addressed through the
+                                   tensor's strides, must be readable memory (src is a
+                                   view into a larger array).  The ghost samples of
+                                   the paper's function tests (f beyond the domain)
+                                   are passed this way, without padding and cropping.
+                                   Accepted by weno_zoom2x and the batched entry
+                                   points; dst must not overlap the extended region. */
+} weno_boundary_t;
+
 typedef struct {
     void* data;              /* device pointer to element [0][0][0][0]              */
     int32_t dtype;           /* weno_dtype_t                                        */
@@ -77,9 +90,10 @@ typedef struct {
                      definitions' h^2/4; the paper's convergence table is
                      reproduced with h^2/8 (the value in the proof of
                      Theorem 1), which callers may pass explicitly.           */
+    int32_t boundary; /* weno_boundary_t                                       */
 } weno_params_t;
 
-/* Default parameters: beta 2, k_eps 1e-8, h 1, nbw -1 (h^2/4). */
+/* Default parameters: beta 2, k_eps 1e-8, h 1, nbw -1 (h^2/4), clamp. */
 weno_params_t weno_default_params(void);
 
 /*

@@ -41,15 +41,25 @@ __all__ = [
 ]
 
 
+_BOUNDARY = {"clamp": _lib.WENO_BOUNDARY_CLAMP, "external": _lib.WENO_BOUNDARY_EXTERNAL}
+
+
 @dataclass(frozen=True)
 class Params:
     beta: float = 2.0
     k_eps: float = 1e-8
     h: float = 1.0
     nbw: float = -1.0  # < 0: h^2 / 4
+    # "clamp": samples beyond the plane are its edge samples; "external": the
+    # input is a view into a larger array whose rows -4 .. H+4 and columns
+    # -4 .. W+4 around it are read as they are (zoom2x and batched only)
+    boundary: str = "clamp"
 
     def c(self) -> WenoParams:
-        return WenoParams(float(self.beta), float(self.k_eps), float(self.h), float(self.nbw))
+        if self.boundary not in _BOUNDARY:
+            raise ValueError("boundary must be 'clamp' or 'external' (got %r)" % (self.boundary,))
+        return WenoParams(float(self.beta), float(self.k_eps), float(self.h), float(self.nbw),
+                          _BOUNDARY[self.boundary])
 
 
 _DT = {torch.uint8: _lib.WENO_U8, torch.float32: _lib.WENO_F32}
@@ -80,9 +90,9 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _params(params, beta, k_eps, h, nbw) -> WenoParams:
+def _params(params, beta, k_eps, h, nbw, boundary="clamp") -> WenoParams:
     if params is None:
-        params = Params(beta=beta, k_eps=k_eps, h=h, nbw=nbw)
+        params = Params(beta=beta, k_eps=k_eps, h=h, nbw=nbw, boundary=boundary)
     return params.c()
 
 
@@ -102,9 +112,9 @@ def _empty_like_layout(x: torch.Tensor, scale: int, dtype) -> torch.Tensor:
 
 
 def zoom2x_(x: torch.Tensor, out: torch.Tensor, params: Params | None = None, *, beta=2.0, k_eps=1e-8,
-            h=1.0, nbw=-1.0) -> torch.Tensor:
+            h=1.0, nbw=-1.0, boundary="clamp") -> torch.Tensor:
     """One WD-WENO doubling of x into the caller's `out` (..., 2H, 2W)."""
-    p = _params(params, beta, k_eps, h, nbw)
+    p = _params(params, beta, k_eps, h, nbw, boundary)
     s, d = _desc(x), _desc(out)
     _lib.check(_lib.lib().weno_zoom2x(ctypes.byref(s), ctypes.byref(d), ctypes.byref(p), _stream(x.device)),
                "weno_zoom2x")
@@ -112,13 +122,15 @@ def zoom2x_(x: torch.Tensor, out: torch.Tensor, params: Params | None = None, *,
 
 
 def zoom2x(x: torch.Tensor, params: Params | None = None, *, out_dtype=None, beta=2.0, k_eps=1e-8, h=1.0,
-           nbw=-1.0) -> torch.Tensor:
+           nbw=-1.0, boundary="clamp") -> torch.Tensor:
     """One WD-WENO doubling: (..., H, W) -> (..., 2H, 2W) in x's layout.
 
     uint8 inputs are read on the [0,1] scale (value/255); `out_dtype` (default:
-    x's dtype) selects uint8 or float32 output."""
+    x's dtype) selects uint8 or float32 output.  boundary="external": x is a
+    view into a larger array and its 4 rows/columns before and 5 after are
+    the samples beyond the plane (the paper's function tests pass f there)."""
     out = _empty_like_layout(x, 2, out_dtype or x.dtype)
-    return zoom2x_(x, out, params, beta=beta, k_eps=k_eps, h=h, nbw=nbw)
+    return zoom2x_(x, out, params, beta=beta, k_eps=k_eps, h=h, nbw=nbw, boundary=boundary)
 
 
 class BatchedZoom:

@@ -15,6 +15,8 @@ WENO_ENOSPC = -4
 WENO_EHIP = -5
 WENO_U8 = 0
 WENO_F32 = 1
+WENO_BOUNDARY_CLAMP = 0
+WENO_BOUNDARY_EXTERNAL = 1
 
 
 class WenoTensor(ctypes.Structure):
@@ -38,6 +40,7 @@ class WenoParams(ctypes.Structure):
         ("k_eps", ctypes.c_float),
         ("h", ctypes.c_float),
         ("nbw", ctypes.c_float),
+        ("boundary", ctypes.c_int32),
     ]
 
 

@@ -34,6 +34,9 @@ __device__ __forceinline__ StripCtx make_ctx(const FwdJob& jb, int n, int c, flo
     cx.d_w = (uint32_t)jb.d_w;
     cx.H = jb.H;
     cx.W = jb.W;
+    cx.src_shift = jb.src_shift;
+    cx.src_h = jb.src_h;
+    cx.src_w = jb.src_w;
     cx.in_u8 = jb.in_u8;
     cx.out_u8 = jb.out_u8;
     cx.vec = jb.vec;
@@ -165,6 +168,7 @@ extern "C" weno_params_t weno_default_params(void)
     p.k_eps = 1e-8f;
     p.h = 1.0f;
     p.nbw = -1.0f;
+    p.boundary = WENO_BOUNDARY_CLAMP;
     return p;
 }
 
@@ -234,6 +238,7 @@ int wz_check_params(const weno_params_t* p)
     if (!(p->k_eps >= 0.0f) || !std::isfinite(p->k_eps)) return WENO_EINVAL;
     if (!(p->h > 0.0f) || !std::isfinite(p->h)) return WENO_EINVAL;
     if (!std::isfinite(p->nbw)) return WENO_EINVAL;
+    if (p->boundary != WENO_BOUNDARY_CLAMP && p->boundary != WENO_BOUNDARY_EXTERNAL) return WENO_EINVAL;
     const double eps = (double)p->k_eps * (double)p->h * (double)p->h;
     // alpha = t^-beta must stay finite in FP32 for t >= eps
     if (p->beta > 0.0f && (eps <= 0.0 || std::log2(eps) * (double)p->beta < -120.0)) return WENO_EINVAL;
@@ -266,7 +271,22 @@ int wz_beta_mode(float beta)
 }
 
 // Fill a FwdJob for src -> dst (shapes already validated).
-FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols, int rows_per_strip)
+// The readable source region of src for a boundary mode: src itself, or
+// (WENO_BOUNDARY_EXTERNAL) rows -4 .. h+4 and columns -4 .. w+4 around it.
+// Returns WENO_EINVAL if that region's start address would wrap.
+int wz_source_region(const weno_tensor_t* src, int boundary, weno_tensor_t* region)
+{
+    *region = *src;
+    if (boundary != WENO_BOUNDARY_EXTERNAL) return WENO_OK;
+    const int64_t back = (4 * src->sh + 4 * src->sw) * wz_esize(src->dtype);
+    if ((uintptr_t)src->data < (uintptr_t)back) return WENO_EINVAL;
+    region->data = (void*)((uintptr_t)src->data - (uintptr_t)back);
+    region->h = src->h + 9;
+    region->w = src->w + 9;
+    return WENO_OK;
+}
+
+FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols, int rows_per_strip, int boundary)
 {
     FwdJob jb;
     const int64_t ei = wz_esize(src->dtype), eo = wz_esize(dst->dtype);
@@ -305,9 +325,28 @@ FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols,
     else if (!jb.in_u8 && jb.out_u8) jb.io = kIoF32U8;
     else if (!vec_rows) jb.io = kIoGeneric;
     else jb.io = jb.in_u8 ? kIoU8F32 : kIoF32;
-    jb.src_extent = (uint32_t)wz_plane_extent(src);
     jb.dst_extent = (uint32_t)wz_plane_extent(dst);
+    weno_tensor_t region;
+    wz_source_region(src, boundary, &region);   // validated by the caller
+    jb.src = (const uint8_t*)region.data;
+    jb.src_extent = (uint32_t)wz_plane_extent(&region);
+    jb.src_shift = boundary == WENO_BOUNDARY_EXTERNAL ? 4 : 0;
+    jb.src_h = region.h;
+    jb.src_w = region.w;
     return jb;
+}
+
+// Checks of a doubling's source region beyond wz_check_pair: with caller
+// ghost samples, the extended region must span less than 2^31 bytes per
+// plane and must not overlap dst.
+int wz_check_region(const weno_tensor_t* src, const weno_tensor_t* dst, int boundary)
+{
+    if (boundary != WENO_BOUNDARY_EXTERNAL) return WENO_OK;
+    weno_tensor_t region;
+    if (wz_source_region(src, boundary, &region) != WENO_OK) return WENO_EINVAL;
+    if (wz_plane_extent(&region) >= (1ll << 31)) return WENO_EINVAL;
+    if (wz_overlap(&region, dst)) return WENO_EOVERLAP;
+    return WENO_OK;
 }
 
 // shape rules of one doubling
@@ -429,7 +468,7 @@ void wz_config_for(const weno_tensor_t* src, int* rows, int* cols)
 int wz_launch_fwd(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, hipStream_t st,
                   int rows, int cols)
 {
-    const FwdJob jb = wz_make_job(src, dst, cols, rows);
+    const FwdJob jb = wz_make_job(src, dst, cols, rows, p->boundary);
     const FwdParams P = wz_fwd_params(p, jb.in_u8, jb.out_u8);
     const int bm = wz_beta_mode(p->beta);
     const hipError_t e = cols == 1 ? launch_fwd_cols<1>(jb, P, bm, rows, st) : launch_fwd_cols<2>(jb, P, bm, rows, st);
@@ -446,6 +485,8 @@ extern "C" int weno_zoom2x(const weno_tensor_t* src, const weno_tensor_t* dst, c
     int rc = wz_check_pair(src, dst, 2);
     if (rc) return rc;
     rc = wz_check_params(p);
+    if (rc) return rc;
+    rc = wz_check_region(src, dst, p->boundary);
     if (rc) return rc;
     int rows, cols;
     wz_config_for(src, &rows, &cols);
@@ -473,6 +514,8 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
     for (int i = 0; i < count; ++i) {
         rc = wz_check_pair(&srcs[i], &dsts[i], 2);
         if (rc) return rc;
+        rc = wz_check_region(&srcs[i], &dsts[i], p->boundary);
+        if (rc) return rc;
     }
     // no output may overlap any input or another output: sweep all byte
     // ranges by start address, remembering the furthest end of each kind
@@ -480,7 +523,9 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
         struct Iv { uintptr_t lo, hi; bool out; };
         std::vector<Iv> iv(2 * (size_t)count);
         for (int i = 0; i < count; ++i) {
-            wz_byte_range(&srcs[i], &iv[2 * i].lo, &iv[2 * i].hi);
+            weno_tensor_t region;   // what the kernel reads of image i
+            wz_source_region(&srcs[i], p->boundary, &region);
+            wz_byte_range(&region, &iv[2 * i].lo, &iv[2 * i].hi);
             iv[2 * i].out = false;
             wz_byte_range(&dsts[i], &iv[2 * i + 1].lo, &iv[2 * i + 1].hi);
             iv[2 * i + 1].out = true;
@@ -512,7 +557,7 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
     int64_t total = 0;
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
-        jobs[k] = wz_make_job(&srcs[i], &dsts[i], cols, rows);
+        jobs[k] = wz_make_job(&srcs[i], &dsts[i], cols, rows, p->boundary);
         prm[k] = wz_fwd_params(p, jobs[k].in_u8, jobs[k].out_u8);
         prefix[k] = total;
         total += (int64_t)jobs[k].planes * jobs[k].strips_x * jobs[k].strips_y;
@@ -623,6 +668,8 @@ extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t
     if (rc) return rc;
     rc = wz_check_params(p);
     if (rc) return rc;
+    // intermediate levels have no caller ghost samples
+    if (p->boundary != WENO_BOUNDARY_CLAMP) return WENO_EINVAL;
     if (dst->n != src->n || dst->c != src->c || (int64_t)dst->h != ((int64_t)src->h << levels) ||
         (int64_t)dst->w != ((int64_t)src->w << levels))
         return WENO_EINVAL;

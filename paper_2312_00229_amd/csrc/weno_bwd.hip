@@ -123,6 +123,8 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     if (x->dtype != WENO_F32 || grad_y->dtype != WENO_F32 || grad_x->dtype != WENO_F32) return WENO_EDTYPE;
     rc = wz_check_params(p);
     if (rc) return rc;
+    // the adjoint folds clamped reads onto the edge pixels; it has no ghost-sample form
+    if (p->boundary != WENO_BOUNDARY_CLAMP) return WENO_EINVAL;
     if (grad_y->n != x->n || grad_y->c != x->c || (int64_t)grad_y->h != 2ll * x->h || (int64_t)grad_y->w != 2ll * x->w)
         return WENO_EINVAL;
     if (grad_x->n != x->n || grad_x->c != x->c || grad_x->h != x->h || grad_x->w != x->w) return WENO_EINVAL;

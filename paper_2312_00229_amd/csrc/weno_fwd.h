@@ -82,6 +82,11 @@ struct FwdJob {
     int32_t vec;                      // 2: float4 rows, 1: float2 rows, 0: scalar stores
     uint32_t src_extent, dst_extent;  // bytes spanned by one plane (< 2^31)
     int32_t io;                       // I/O mode (kIo*)
+    // readable source region: src points at its element (0, 0), which is
+    // image element (-src_shift, -src_shift); reads clamp to src_h x src_w
+    // (clamp-to-edge: shift 0 and the image; caller ghost samples: shift 4
+    // and (H + 9) x (W + 9))
+    int32_t src_shift, src_h, src_w;
 };
 
 __device__ __forceinline__ float from_left(float x)
@@ -210,6 +215,7 @@ struct StripCtx {
     uint32_t s_h, d_h, d_w;   // byte strides: source rows, destination rows, destination columns
     uint32_t s_w_bytes;       // source column stride
     int32_t H, W;
+    int32_t src_shift, src_h, src_w;   // readable source region (FwdJob)
     int32_t in_u8, out_u8, vec;
     float out_scale;
 };
@@ -225,7 +231,8 @@ using raw_t = typename std::conditional<io_in_u8(IO), uint8_t, uint32_t>::type;
 template <int COLS, int IO>
 __device__ __forceinline__ void load_row_raw(const StripCtx& cx, const uint32_t (&off)[COLS], int r, raw_t<IO> (&q)[COLS])
 {
-    const int rc = r < 0 ? 0 : (r >= cx.H ? cx.H - 1 : r);
+    const int rs = r + cx.src_shift;
+    const int rc = rs < 0 ? 0 : (rs >= cx.src_h ? cx.src_h - 1 : rs);
     const uint32_t soff = (uint32_t)rc * cx.s_h;
     const bool u8 = io_in_u8(IO) || (IO == kIoGeneric && cx.in_u8);
     if (u8) {
@@ -537,7 +544,8 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
         L.J[c] = Jbase + sidx_;
         L.own[c] = (sidx_ >= HALO_L) && (sidx_ < HALO_L + OWN) && (L.J[c] < cx.W);
         L.own_all = L.own_all && L.own[c];
-        const int jc = L.J[c] < 0 ? 0 : (L.J[c] >= cx.W ? cx.W - 1 : L.J[c]);
+        const int js = L.J[c] + cx.src_shift;
+        const int jc = js < 0 ? 0 : (js >= cx.src_w ? cx.src_w - 1 : js);
         L.src_off[c] = (uint32_t)jc * cx.s_w_bytes;
         L.st_col[c] = L.own[c] ? (uint32_t)(2 * L.J[c]) * cx.d_w : kOob;
     }

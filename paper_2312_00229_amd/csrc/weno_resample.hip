@@ -692,6 +692,7 @@ extern "C" int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst,
     if (rc) return rc;
     rc = wz_check_params(p);
     if (rc) return rc;
+    if (p->boundary != WENO_BOUNDARY_CLAMP) return WENO_EINVAL;   // samples beyond the ends are clamped
     if (!d_workspace) return WENO_EINVAL;
     if (ws_bytes < weno_resample_workspace(src, dst)) return WENO_ENOSPC;
     return run_resample(src, dst, p, p->h, (uint8_t*)d_workspace, (hipStream_t)hip_stream);
@@ -722,6 +723,7 @@ extern "C" int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, 
     if (rc) return rc;
     rc = wz_check_params(p);
     if (rc) return rc;
+    if (p->boundary != WENO_BOUNDARY_CLAMP) return WENO_EINVAL;   // samples beyond the ends are clamped
     if (!d_workspace) return WENO_EINVAL;
     if (ws_bytes < weno_zoom_to_workspace(src, dst)) return WENO_ENOSPC;
     hipStream_t st = (hipStream_t)hip_stream;

@@ -172,3 +172,34 @@ def test_status_strings():
     for s in (0, -1, -2, -3, -4, -5, -99):
         assert isinstance(_lib.status_string(s), str)
     assert _lib.lib().weno_version().decode().count(".") == 2
+
+
+def _pb(boundary):
+    p = _p()
+    p.boundary = boundary
+    return p
+
+
+def test_boundary_mode_validation():
+    L = _lib.lib()
+    src, dst = _t(ptr=0x100000), _t(ptr=0x200000, h=8, w=10)
+    assert call_zoom(src, dst, _pb(2)) == _lib.WENO_EINVAL
+    assert call_zoom(src, dst, _pb(-1)) == _lib.WENO_EINVAL
+    ext = _pb(_lib.WENO_BOUNDARY_EXTERNAL)
+    # the ghost region starts 4 rows and 4 columns before element 0: it must
+    # not wrap below address 0 ...
+    assert call_zoom(_t(ptr=16), dst, ext) == _lib.WENO_EINVAL
+    # ... nor overlap the output where the 4 x 5 plane itself does not: the
+    # region (rows and columns -4 .. 8 of 5-float rows) spans floats -24 .. 48
+    # of the plane, which itself spans floats 0 .. 19
+    assert call_zoom(_t(ptr=0x100000), _t(ptr=0x100000 + 4 * 40, h=8, w=10), ext) == _lib.WENO_EOVERLAP
+    assert call_zoom(_t(ptr=0x100000), _t(ptr=0x100000 - 4 * 84, h=8, w=10), ext) == _lib.WENO_EOVERLAP
+    # entry points without ghost samples reject the mode before anything else
+    c = ctypes.byref
+    s3, d3 = _t(ptr=0x100000, h=4, w=5), _t(ptr=0x800000, h=32, w=40)
+    assert L.weno_zoom2x_cascade(c(s3), c(d3), 3, c(ext), 0x400000, 1 << 20, None) == _lib.WENO_EINVAL
+    r = _t(ptr=0x800000, h=7, w=9)
+    assert L.weno_resample(c(src), c(r), c(ext), 0x400000, 1 << 20, None) == _lib.WENO_EINVAL
+    assert L.weno_zoom_to(c(src), c(r), c(ext), 0x400000, 1 << 20, None) == _lib.WENO_EINVAL
+    g, gx = _t(ptr=0x200000, h=8, w=10), _t(ptr=0x300000)
+    assert L.weno_zoom2x_backward(c(src), c(g), c(gx), c(ext), None) == _lib.WENO_EINVAL

@@ -218,3 +218,40 @@ def test_padded_output_rows_untouched(gpu, cfg, W, dtypes):
     else:
         assert np.abs(got - ref).max() <= TOL
         assert bool((big[:, 2 * W:] == -7.0).all())
+
+
+@pytest.mark.parametrize("shape", [(9, 11), (40, 141), (3, 300)])
+def test_external_boundary_f32(gpu, shape):
+    # the input is a view into a larger array; its 4 rows/columns before and
+    # 5 after are the samples beyond the plane: the result is the doubling of
+    # that (H + 9) x (W + 9) region, cropped
+    _set(gpu, (0, 0))
+    H, W = shape
+    E = random_plane(H + 12, W + 15, seed=H + W, kind="steps").astype(np.float32)
+    r0, c0 = 5, 7   # the view starts at E[r0, c0]; rows r0-4 .. r0+H+4 are read
+    Et = _f32(E)
+    U = gpu.zoom2x(Et[r0:r0 + H, c0:c0 + W], boundary="external").cpu().numpy()
+    region = E[r0 - 4:r0 + H + 5, c0 - 4:c0 + W + 5]
+    ref = oracle.zoom2x(region.astype(np.float64))[8:8 + 2 * H, 8:8 + 2 * W]
+    assert np.abs(U - ref).max() <= TOL
+    assert np.array_equal(U[0::2, 0::2], E[r0:r0 + H, c0:c0 + W])
+    # and bit for bit the library's own doubling of the region, cropped
+    full = gpu.zoom2x(_f32(region)).cpu().numpy()[8:8 + 2 * H, 8:8 + 2 * W]
+    assert np.array_equal(U, full)
+
+
+def test_external_boundary_u8_hwc_and_batched(gpu):
+    _set(gpu, (0, 0))
+    img = scene_rgb(70, 130, seed=4, n_polygons=6)
+    big = torch.tensor(img, device="cuda")
+    r0, c0, H, W = 6, 9, 50, 111
+    view = big[r0:r0 + H, c0:c0 + W].permute(2, 0, 1)
+    y = gpu.zoom2x(view, boundary="external").cpu().numpy()
+    region = big[r0 - 4:r0 + H + 5, c0 - 4:c0 + W + 5].permute(2, 0, 1).contiguous()
+    full = gpu.zoom2x(region).cpu().numpy()[:, 8:8 + 2 * H, 8:8 + 2 * W]
+    assert np.array_equal(y, full)
+    # the batched entry point reads the same ghost samples
+    outs = [torch.empty((2 * H, 2 * W, 3), dtype=torch.uint8, device="cuda").permute(2, 0, 1) for _ in range(2)]
+    gpu.BatchedZoom([view, view], outs, gpu.Params(boundary="external")).run()
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), y)

@@ -5,7 +5,8 @@ Same readings as the oracle's reproduction: the table's h is the spacing of
 the zoomed grid (input spacing 2h); samples outside the domain are f itself,
 supplied by padding the input with M ghost samples per side and cropping the
 output (a quad reads inputs I-4..I+5, so M = 6 leaves the cropped outputs
-independent of the clamped edge); neighbour weight h_in^2/8.
+independent of the clamped edge), or read in place through the library's
+external boundary; neighbour weight h_in^2/8.
 
 FP32 resolves the errors of rows 1-7 (row 7's 2.36e-6 is ~40 ulp of f ~ 1);
 the finer rows are below FP32 rounding and are pinned on the oracle only."""
@@ -29,14 +30,25 @@ def f1(x, y):
     return 1.0 / (x * x + y * y + 1.0)
 
 
-def gpu_linf(gpu, i):
+def gpu_zoom(gpu, i, boundary="pad"):
+    """The zoomed (2n-1)^2 grid of row i: ghost samples by padding and
+    cropping, or read in place (boundary "external": the input is the n x n
+    view of the padded array)."""
     ht = 2.0 ** (-i)
     hin = 2 * ht
     n = int(round(2 / hin)) + 1
     x = -1 + np.arange(-M, n + M) * hin
-    V = f1(x[:, None], x[None, :]).astype(np.float32)
-    U = gpu.zoom2x(torch.tensor(V, device="cuda"), beta=1.0, k_eps=1e-8, h=hin, nbw=hin * hin / 8.0)
-    U = U.cpu().numpy().astype(np.float64)[2 * M: 2 * M + 2 * n - 1, 2 * M: 2 * M + 2 * n - 1]
+    V = torch.tensor(f1(x[:, None], x[None, :]).astype(np.float32), device="cuda")
+    kw = dict(beta=1.0, k_eps=1e-8, h=hin, nbw=hin * hin / 8.0)
+    if boundary == "pad":
+        U = gpu.zoom2x(V, **kw)[2 * M: 2 * M + 2 * n - 1, 2 * M: 2 * M + 2 * n - 1]
+    else:
+        U = gpu.zoom2x(V[M: M + n, M: M + n], boundary="external", **kw)[: 2 * n - 1, : 2 * n - 1]
+    return U.cpu().numpy().astype(np.float64), ht, n
+
+
+def gpu_linf(gpu, i, boundary="pad"):
+    U, ht, n = gpu_zoom(gpu, i, boundary)
     xo = -1 + np.arange(2 * n - 1) * ht
     return np.abs(U - f1(xo[:, None], xo[None, :])).max()
 
@@ -44,6 +56,17 @@ def gpu_linf(gpu, i):
 def test_row1_is_12_over_19(gpu):
     # the centre x point of the 2x2 grid {-1, 1}^2 is 7/19, so the error is 12/19
     assert abs(gpu_linf(gpu, 0) - 12.0 / 19.0) <= 1e-6
+
+
+@pytest.mark.parametrize("i", range(4))
+def test_ghost_samples_read_in_place(gpu, i):
+    # the library's external boundary reads the ghost samples through the
+    # view's strides: the same arithmetic as padding and cropping, bit for bit
+    Ue, _, _ = gpu_zoom(gpu, i, "external")
+    Up, _, _ = gpu_zoom(gpu, i, "pad")
+    assert np.array_equal(Ue, Up)
+    if i == 0:
+        assert abs(gpu_linf(gpu, 0, "external") - 12.0 / 19.0) <= 1e-6
 
 
 @pytest.mark.parametrize("i", range(7))
