@@ -294,7 +294,8 @@ __global__ __launch_bounds__(256) void cols_pass_kernel(ColPassArgs a, const Sam
 // both forms give the same bits.  The host picks M and tw so that a tile's
 // span i(c_last) - i(c0) + 4 fits in 256 M samples.
 constexpr int kFuseQ = 3;          // output columns per thread at most (tw <= 768)
-constexpr int kFuseMaxTw = 256 * kFuseQ;
+constexpr int kFuseThreads = 256;  // threads per block (LDS slots per row: kFuseThreads M)
+constexpr int kFuseMaxTw = kFuseThreads * kFuseQ;
 
 struct FusedArgs {
     const uint8_t* src;
@@ -308,10 +309,10 @@ struct FusedArgs {
 };
 
 template <int BETA, int M, bool IN_U8, bool OUT_U8>
-__global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const SamplePos* __restrict__ prow,
+__global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs a, const SamplePos* __restrict__ prow,
                                                              const SamplePos* __restrict__ pcol)
 {
-    __shared__ float row_buf[2][256 * M];
+    __shared__ float row_buf[2][kFuseThreads * M];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tile = blockIdx.x;
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const 
     // row phase: the input columns of this thread's LDS slots
     uint32_t vin[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) vin[m] = (uint32_t)min(max(xa + tid + 256 * m, 0), a.in_w - 1) * a.s_w;
+    for (int m = 0; m < M; ++m) vin[m] = (uint32_t)min(max(xa + tid + kFuseThreads * m, 0), a.in_w - 1) * a.s_w;
     // column phase: per output column, the LDS index of its first tap and its weights
     int lb[kFuseQ];
     uint32_t vout[kFuseQ];
@@ -333,8 +334,8 @@ __global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const 
     int live = 0;   // bit q: the wave owns a column of slot q (uniform)
 #pragma unroll
     for (int q = 0; q < kFuseQ; ++q) {
-        const int c = c0 + tid + 256 * q;
-        live |= (c0 + 256 * q + 64 * wave < c1) << q;
+        const int c = c0 + tid + kFuseThreads * q;
+        live |= (c0 + kFuseThreads * q + 64 * wave < c1) << q;
         const SamplePos p = pcol[min(c, a.out_w - 1)];
         lb[q] = p.i - 1 - xa;
         vout[q] = c < c1 ? (uint32_t)c * a.d_w : kOob;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void fused_resample_kernel(FusedArgs a, const 
             const float tt = At, ss = tt - 1.0f, htt = 0.5f * tt, hss = 0.5f * ss;
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                buf[tid + 256 * m] = blend<BETA>((float)A[m][0], (float)A[m][1], (float)A[m][2], (float)A[m][3], tt, ss,
+                buf[tid + kFuseThreads * m] = blend<BETA>((float)A[m][0], (float)A[m][1], (float)A[m][2], (float)A[m][3], tt, ss,
                                                  htt, hss, Ak, a.eps4_in, a.beta) *
                                      kScale;
         }
@@ -517,7 +518,7 @@ FusedShape fused_shape(int n_in, int n_out)
     const int64_t num = n_in > 1 ? n_in - 1 : 0, den = n_out > 1 ? n_out - 1 : 1;
     const int64_t min_tw = n_out < 64 ? n_out : 64;
     for (int m = 2; m <= 4; ++m) {
-        int64_t twmax = num == 0 ? kFuseMaxTw : (256ll * m - 4) * den / num + 1;
+        int64_t twmax = num == 0 ? kFuseMaxTw : ((int64_t)kFuseThreads * m - 4) * den / num + 1;
         if (twmax > kFuseMaxTw) twmax = kFuseMaxTw;
         if (twmax < min_tw) continue;
         const int64_t tiles = (n_out + twmax - 1) / twmax;
@@ -542,13 +543,13 @@ void launch_fused_typed(const FusedArgs& a, bool in_u8, bool out_u8, dim3 grid, 
                         const SamplePos* pcol, hipStream_t st)
 {
     if (in_u8 && out_u8)
-        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, true, true>), grid, dim3(256), 0, st, a, prow, pcol);
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, true, true>), grid, dim3(kFuseThreads), 0, st, a, prow, pcol);
     else if (in_u8)
-        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, true, false>), grid, dim3(256), 0, st, a, prow, pcol);
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, true, false>), grid, dim3(kFuseThreads), 0, st, a, prow, pcol);
     else if (out_u8)
-        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, false, true>), grid, dim3(256), 0, st, a, prow, pcol);
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, false, true>), grid, dim3(kFuseThreads), 0, st, a, prow, pcol);
     else
-        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, false, false>), grid, dim3(256), 0, st, a, prow, pcol);
+        hipLaunchKernelGGL((fused_resample_kernel<BETA, M, false, false>), grid, dim3(kFuseThreads), 0, st, a, prow, pcol);
 }
 
 template <int BETA>
