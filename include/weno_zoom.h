@@ -149,8 +149,8 @@ int weno_zoom2x_batched(const weno_tensor_t* srcs, const weno_tensor_t* dsts, in
  * `levels` successive doublings (eq. zoomfactor), FP32 intermediates in the
  * caller's workspace, the grid spacing halved at each level (h, h/2, ...).
  *   src: (n, c, h, w); dst: (n, c, 2^levels h, 2^levels w); 1 <= levels <= 8.
- *   d_workspace: DEVICE memory of at least
- *                weno_zoom2x_cascade_workspace(src, levels) bytes.
+ *   d_workspace: DEVICE memory, 256-byte aligned (as hipMalloc returns), of
+ *                at least weno_zoom2x_cascade_workspace(src, levels) bytes.
  * Only kernels are enqueued (no copies, no allocation), so the call can be
  * captured into a hipGraph and replayed.
  */
@@ -167,8 +167,8 @@ int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t* dst, int3
  * at input coordinate j (h_in - 1)/(h_out - 1); samples on input nodes are
  * copied exactly; samples beyond the ends are clamped.  eps = k_eps h^2 as for
  * the doubling (nbw is unused).
- *   d_workspace: DEVICE memory of at least weno_resample_workspace(src, dst)
- *                bytes: the positions of the H rows and W columns and, only
+ *   d_workspace: DEVICE memory, 256-byte aligned, of at least
+ *                weno_resample_workspace(src, dst) bytes: the positions of the H rows and W columns and, only
  *                where (w - 1)/(W - 1) exceeds about 16, an FP32
  *                (n, c, H, w + 3) intermediate.  Kernels only: capturable.
  */
@@ -183,8 +183,9 @@ int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst, const weno
  * previous level with the spacing halved, then weno_resample of the
  * (2^k (h-1) + 1) x (2^k (w-1) + 1) grid to (H, W).  k = 0 (a target no larger
  * than the source) is plain resampling.
- *   d_workspace: DEVICE memory of at least weno_zoom_to_workspace(src, dst)
- *                bytes (FP32 intermediates).  Kernels only: capturable.
+ *   d_workspace: DEVICE memory, 256-byte aligned, of at least
+ *                weno_zoom_to_workspace(src, dst) bytes (FP32 intermediates and
+ *                the resampler's workspace).  Kernels only: capturable.
  */
 size_t weno_zoom_to_workspace(const weno_tensor_t* src, const weno_tensor_t* dst);
 int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, void* d_workspace,

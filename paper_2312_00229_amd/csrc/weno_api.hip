@@ -675,7 +675,7 @@ extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t
         return WENO_EINVAL;
     if (wz_overlap(src, dst)) return WENO_EOVERLAP;
     if (levels > 1) {
-        if (!d_workspace) return WENO_EINVAL;
+        if (!d_workspace || (uintptr_t)d_workspace % 256 != 0) return WENO_EINVAL;
         if (ws_bytes < weno_zoom2x_cascade_workspace(src, levels)) return WENO_ENOSPC;
     }
     weno_tensor_t cur = *src;

@@ -322,11 +322,15 @@ __global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs 
     const rsrc_t src = make_rsrc(a.src + n * a.s_n + ch * a.s_c, a.src_extent);
     const rsrc_t dst = make_rsrc(a.dst + n * a.d_n + ch * a.d_c, a.d_extent);
     const int c0 = ct * a.tw, c1 = min(c0 + a.tw, a.out_w);
-    const int xa = pcol[c0].i - 1;
-    // row phase: the input columns of this thread's LDS slots
+    const int xa = pcol[c0].i - 1, xb = pcol[c1 - 1].i + 2;   // the tile's span of input columns
+    // row phase: the input columns of this thread's LDS slots (slots past the
+    // span load nothing: their values are never read)
     uint32_t vin[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) vin[m] = (uint32_t)min(max(xa + tid + kFuseThreads * m, 0), a.in_w - 1) * a.s_w;
+    for (int m = 0; m < M; ++m) {
+        const int x = xa + tid + kFuseThreads * m;
+        vin[m] = x <= xb ? (uint32_t)min(max(x, 0), a.in_w - 1) * a.s_w : kOob;
+    }
     // column phase: per output column, the LDS index of its first tap and its weights
     int lb[kFuseQ];
     uint32_t vout[kFuseQ];
@@ -694,7 +698,7 @@ extern "C" int weno_resample(const weno_tensor_t* src, const weno_tensor_t* dst,
     rc = wz_check_params(p);
     if (rc) return rc;
     if (p->boundary != WENO_BOUNDARY_CLAMP) return WENO_EINVAL;   // samples beyond the ends are clamped
-    if (!d_workspace) return WENO_EINVAL;
+    if (!d_workspace || (uintptr_t)d_workspace % 256 != 0) return WENO_EINVAL;   // tables and planes are aligned
     if (ws_bytes < weno_resample_workspace(src, dst)) return WENO_ENOSPC;
     return run_resample(src, dst, p, p->h, (uint8_t*)d_workspace, (hipStream_t)hip_stream);
 }
@@ -725,7 +729,7 @@ extern "C" int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, 
     rc = wz_check_params(p);
     if (rc) return rc;
     if (p->boundary != WENO_BOUNDARY_CLAMP) return WENO_EINVAL;   // samples beyond the ends are clamped
-    if (!d_workspace) return WENO_EINVAL;
+    if (!d_workspace || (uintptr_t)d_workspace % 256 != 0) return WENO_EINVAL;   // tables and planes are aligned
     if (ws_bytes < weno_zoom_to_workspace(src, dst)) return WENO_ENOSPC;
     hipStream_t st = (hipStream_t)hip_stream;
     const int k = zoom_levels(src, dst);

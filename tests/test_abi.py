@@ -203,3 +203,15 @@ def test_boundary_mode_validation():
     assert L.weno_zoom_to(c(src), c(r), c(ext), 0x400000, 1 << 20, None) == _lib.WENO_EINVAL
     g, gx = _t(ptr=0x200000, h=8, w=10), _t(ptr=0x300000)
     assert L.weno_zoom2x_backward(c(src), c(g), c(gx), c(ext), None) == _lib.WENO_EINVAL
+
+
+def test_workspace_alignment():
+    # position tables and float planes in the workspace need 256-byte alignment
+    L = _lib.lib()
+    c = ctypes.byref
+    src, p = _t(ptr=0x100000), _p()
+    r = _t(ptr=0x800000, h=7, w=9)
+    assert L.weno_resample(c(src), c(r), c(p), 0x400000 + 16, 1 << 20, None) == _lib.WENO_EINVAL
+    assert L.weno_zoom_to(c(src), c(r), c(p), 0x400000 + 16, 1 << 20, None) == _lib.WENO_EINVAL
+    d3 = _t(ptr=0x800000, h=32, w=40)
+    assert L.weno_zoom2x_cascade(c(src), c(d3), 3, c(p), 0x400000 + 16, 1 << 20, None) == _lib.WENO_EINVAL
