@@ -30,12 +30,12 @@
 //   output      dL/dV row s-4 is complete: fold clamped rows/columns onto the
 //               edge pixels and store.
 // Valid lanes shrink with every neighbour access: the dL/dV of lanes 9..54 is
-// exact.  A strip owns up to 42 columns: the first strip of a row starts at
-// lane 13 so that the four padded columns left of the image (folded onto
-// column 0) fall in lanes 9..12; the others start at lane 9, which leaves
-// lanes up to 54 for the four padded columns right of the image in the last
-// strip.  A strip that is both first and last holds at most 38 columns, so
-// images 39..42 wide are split into two strips of 21.
+// exact.  The first strip of a row starts at lane 13 so that the four padded
+// columns left of the image (folded onto column 0) fall in lanes 9..12 and
+// owns 42 columns; the last starts at lane 9 and owns at most 42, which leaves
+// lanes up to 54 for the four padded columns right of the image; the strips
+// between own all 46 exact lanes.  A strip that is both first and last holds
+// at most 38 columns, so images 39..42 wide are split into two strips of 21.
 #pragma once
 
 #include <stdint.h>
@@ -44,12 +44,58 @@
 
 namespace wz {
 
-constexpr int kBwdOwn = 42;        // columns stored per strip
 constexpr int kBwdLane0First = 13; // lane of the first owned column, first strip of a row
 constexpr int kBwdLane0 = 9;       // lane of the first owned column, other strips
+constexpr int kBwdOwnFirst = 42;   // columns of the first strip of a row (lanes 13..54)
+constexpr int kBwdOwnMid = 46;     // columns of a strip between the first and the last (lanes 9..54)
+constexpr int kBwdOwnLast = 42;    // at most, in the last strip (its padding takes lanes up to 54)
 
-// columns per strip for an image W wide (host and device)
-__host__ __device__ inline int bwd_strip_width(int W) { return (W >= 39 && W <= 42) ? 21 : kBwdOwn; }
+// Strip layout along a row of W columns (host and device).  The exact lanes
+// of a strip are 9..54.  The first strip owns columns from lane 13 (lanes
+// 9..12 carry the four padded columns left of the image), the last owns at
+// most 42 so that the four padded columns right of the image fall in lanes up
+// to 54, and strips in between own all 46.  A strip that is both first and
+// last holds at most 38 columns: widths 39..42 are two strips of 21.
+__host__ __device__ inline int bwd_strip_count(int W)
+{
+    if (W <= 38) return 1;
+    if (W <= 42) return 2;
+    const int R = W - kBwdOwnFirst;   // columns after the first strip
+    if (R <= kBwdOwnLast) return 2;
+    return 2 + (R - kBwdOwnLast + kBwdOwnMid - 1) / kBwdOwnMid;
+}
+
+// first column c0 and width of strip sx of a row of W columns
+__host__ __device__ inline void bwd_strip_span(int W, int sx, int& c0, int& width)
+{
+    if (W <= 38) {
+        c0 = 0;
+        width = W;
+        return;
+    }
+    if (W <= 42) {
+        c0 = 21 * sx;
+        width = sx == 0 ? 21 : W - 21;
+        return;
+    }
+    if (sx == 0) {
+        c0 = 0;
+        width = kBwdOwnFirst;
+        return;
+    }
+    const int n = bwd_strip_count(W), mid = n - 2;
+    // the last strip takes what the middle ones leave, at least one column
+    // (the last middle strip gives up what that needs)
+    const int r = W - kBwdOwnFirst - kBwdOwnMid * mid;
+    const int last = r < 1 ? 1 : r;
+    if (sx == n - 1) {
+        c0 = W - last;
+        width = last;
+        return;
+    }
+    c0 = kBwdOwnFirst + kBwdOwnMid * (sx - 1);
+    width = sx < n - 2 ? kBwdOwnMid : (W - last) - c0;
+}
 
 // Iterations before the first exact dL/dV row.  A walk that starts at row a
 // (windows holding fill values) has exact V rows from a+5, second differences
@@ -128,8 +174,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int H = cx.H, W = cx.W;
-    const int width = bwd_strip_width(W);
-    const int c0 = strip_x * width;
+    int c0, width;
+    bwd_strip_span(W, strip_x, c0, width);
     const int lane0 = strip_x == 0 ? kBwdLane0First : kBwdLane0;
     const int J = c0 - lane0 + lane;
     const bool own = lane >= lane0 && lane < lane0 + width && J < W;

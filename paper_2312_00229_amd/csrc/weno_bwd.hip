@@ -150,7 +150,7 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     cx.H = x->h;
     cx.W = x->w;
     const FwdParams P = wz_fwd_params(p, 0, 0);
-    const int strips_x = (x->w + bwd_strip_width(x->w) - 1) / bwd_strip_width(x->w);
+    const int strips_x = bwd_strip_count(x->w);
     const int64_t planes = (int64_t)x->n * x->c;
     int rows = bwd_auto_rows(x->h, strips_x, planes, bwd_resident_blocks());
     const int explicit_rows = g_bwd_rows.load();

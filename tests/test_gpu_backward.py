@@ -30,8 +30,10 @@ def _close(got, ref):
 
 
 SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (7, 77), (40, 39), (65, 120), (130, 37), (64, 38), (3, 200),
-          # strip-width boundaries: one strip up to 38 columns, two of 21 for 39..42, then 42 per strip
-          (6, 42), (5, 43), (11, 84), (9, 85), (12, 126), (7, 127)]
+          # strip layout boundaries: one strip up to 38 columns, two of 21 for 39..42, first + last (42 + up
+          # to 42) up to 84, then middle strips of 46 (85: 42 | 42 | 1, 130: 42 | 46 | 42, 131: 42 | 46 |
+          # 42 | 1, 177/178: three or four strips)
+          (6, 42), (5, 43), (11, 84), (9, 85), (12, 126), (7, 127), (6, 130), (5, 131), (4, 177), (3, 178)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
