@@ -5,7 +5,9 @@ to 23170 x 23170 floats (2,147,395,600 bytes, just under 2^31); a
 23170 x 23170 uint8 plane doubles to the same byte count.  Sampled windows
 -- the four corners, the last rows and columns, interior points -- are
 checked against the oracle on windows of the input, in the automatic launch
-configuration (the benchmark's)."""
+configuration (the benchmark's).  The resampler is checked at both limits: upsampling into a
+23170 x 23170 float plane and downsampling out of one, on sampled rows and
+columns."""
 import numpy as np
 import pytest
 import torch
@@ -77,4 +79,38 @@ def test_backward_largest_plane(gpu):
         got = gx[r0:r1, c0:c1].cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max()), (r0, c0)
     del x, g, gx
+    torch.cuda.empty_cache()
+
+
+def _resample_samples(xs, OH, OW, rows, cols):
+    """Oracle outputs of the tensor resampler of the float32 plane xs at
+    (rows x cols): each sampled output row from its four clamped tap rows
+    (the 1D spline on a 4-row array at local position 1 + t), then along it."""
+    from oracle import resample as R
+
+    H, W = xs.shape
+    px, py = R.grid_positions(H, OH), R.grid_positions(W, OW)
+    out = np.empty((len(rows), len(cols)))
+    for k, r in enumerate(rows):
+        i = min(max(int(np.floor(px[r])), 0), max(H - 2, 0))
+        taps = xs[[min(max(j, 0), H - 1) for j in (i - 1, i, i + 1, i + 2)]].astype(np.float64)
+        z = R.weno1d_eval(taps, [1.0 + (px[r] - i)], axis=-2)[0]
+        out[k] = R.weno1d_eval(z, py[cols])
+    return out
+
+
+@pytest.mark.parametrize("shape,out", [((15447, 15447), (23170, 23170)),    # output plane just under 2^31 bytes
+                                       ((23170, 23170), (11585, 11585))])   # input plane just under 2^31 bytes
+def test_resample_largest_planes(gpu, shape, out):
+    xs = np.random.default_rng(35).random(shape, dtype=np.float32)
+    x = torch.from_numpy(xs).cuda()
+    y = gpu.resample(x, *out)
+    assert max(x.numel(), y.numel()) * 4 < 2 ** 31
+    OH, OW = out
+    rows = [0, 1, OH // 2 + 3, OH - 2, OH - 1]
+    cols = list(range(0, 130)) + list(range(OW // 2 - 65, OW // 2 + 65)) + list(range(OW - 130, OW))
+    ref = _resample_samples(xs, OH, OW, rows, cols)
+    got = y[rows][:, cols].cpu().numpy()
+    assert np.abs(got - ref).max() <= TOL
+    del x, y
     torch.cuda.empty_cache()
