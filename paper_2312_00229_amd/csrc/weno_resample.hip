@@ -357,37 +357,73 @@ __global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs 
         if constexpr (IN_U8) return __builtin_amdgcn_raw_buffer_load_b8(src, (int)voff, (int)soff, 0);
         else return buf_ld_f32(src, voff, soff);
     };
-    raw A[M][4];
-    float At = 0.0f, Ak = 0.0f;
-    auto load = [&](int r) {
-        const SamplePos p = prow[r];
-        const uint32_t s0 = (uint32_t)p.i * a.s_h;
-        const bool node = p.node != 0;   // four taps on the node's row: the blend returns it exactly
-        const uint32_t sm = node ? s0 : (uint32_t)max(p.i - 1, 0) * a.s_h;
-        const uint32_t s1 = node ? s0 : s0 + a.s_h;
-        const uint32_t s2 = node ? s0 : (uint32_t)min(p.i + 2, a.in_h - 1) * a.s_h;
+    // The row phase slides a window of input rows down the run: W holds rows
+    // cur - 1 .. cur + 2 (clamped) at this thread's LDS slots.  Output rows
+    // advance the interval by d = i(r + 1) - i(r) >= 0 (uniform), so moving
+    // to the next row keeps 4 - d rows and loads d of them (all four past 3):
+    // about 1.33 loads per output row when downsampling by 4/3, against four.
+    raw W[M][4];
+    int cur = 0;
+    auto row_off = [&](int k) { return (uint32_t)min(max(k, 0), a.in_h - 1) * a.s_h; };
+    auto ld_row = [&](int slot, int k) {
+        const uint32_t so = row_off(k);
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            A[m][0] = ld(vin[m], sm);
-            A[m][1] = ld(vin[m], s0);
-            A[m][2] = ld(vin[m], s1);
-            A[m][3] = ld(vin[m], s2);
+        for (int m = 0; m < M; ++m) W[m][slot] = ld(vin[m], so);
+    };
+    auto advance = [&](int i) {
+        const int d = i - cur;
+        if (d == 1) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                W[m][0] = W[m][1];
+                W[m][1] = W[m][2];
+                W[m][2] = W[m][3];
+            }
+            ld_row(3, i + 2);
+        } else if (d == 2) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                W[m][0] = W[m][2];
+                W[m][1] = W[m][3];
+            }
+            ld_row(2, i + 1);
+            ld_row(3, i + 2);
+        } else if (d == 3) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) W[m][0] = W[m][3];
+            ld_row(1, i);
+            ld_row(2, i + 1);
+            ld_row(3, i + 2);
+        } else if (d != 0) {
+            ld_row(0, i - 1);
+            ld_row(1, i);
+            ld_row(2, i + 1);
+            ld_row(3, i + 2);
         }
-        At = p.t;
-        Ak = p.k;
+        cur = i;
     };
     const int r0 = rr * a.run, r1 = min(r0 + a.run, a.out_h);
+    SamplePos pc = prow[r0];   // the row being resampled
+    cur = pc.i;
+    ld_row(0, cur - 1);
+    ld_row(1, cur);
+    ld_row(2, cur + 1);
+    ld_row(3, cur + 2);
     auto step = [&](int r, float* buf) {
         {
-            const float tt = At, ss = tt - 1.0f, htt = 0.5f * tt, hss = 0.5f * ss;
+            // a node row (t = 0, omega_1 masked) is its own tap W[1], exactly
+            const float tt = pc.t, ss = tt - 1.0f, htt = 0.5f * tt, hss = 0.5f * ss;
+            const float wm = pc.node ? 0.0f : 1.0f;
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                buf[tid + kFuseThreads * m] = blend<BETA>((float)A[m][0], (float)A[m][1], (float)A[m][2], (float)A[m][3], tt, ss,
-                                                 htt, hss, Ak, a.eps4_in, a.beta) *
-                                     kScale;
+                buf[tid + kFuseThreads * m] = blend<BETA>((float)W[m][0], (float)W[m][1], (float)W[m][2],
+                                                          (float)W[m][3], tt, ss, htt, hss, pc.k, a.eps4_in, a.beta,
+                                                          wm) *
+                                              kScale;
         }
         __syncthreads();
-        load(min(r + 1, r1 - 1));
+        pc = prow[min(r + 1, r1 - 1)];
+        advance(pc.i);
         // uniform (kept in a scalar register: a buffer store's row offset)
         const uint32_t so = __builtin_amdgcn_readfirstlane((uint32_t)r * a.d_h);
 #pragma unroll
@@ -399,7 +435,6 @@ __global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs 
             else buf_st_f32(u, dst, vout[q], so);
         }
     };
-    load(r0);
     int r = r0;
     for (; r + 2 <= r1; r += 2) {
         step(r, row_buf[0]);
