@@ -139,3 +139,15 @@ def test_resample_nodes_are_copies(gpu):
     V = random_plane(123, 301, seed=9, kind="uniform").astype(np.float32)
     got = gpu.resample(_t(V), 245, 601).cpu().numpy()
     assert np.array_equal(got[::2, ::2], V)
+
+
+@pytest.mark.parametrize("shape,out", [((400, 300), (37, 250)), ((301, 64), (99, 64)), ((64, 40), (16, 40))])
+def test_resample_row_window_steps(gpu, shape, out):
+    # vertical ratios 11.1, 3.06 and 4.2: consecutive output rows advance the
+    # interval by 3 or 4 and more rows, the window steps that reload most or
+    # all of its rows
+    V = random_plane(*shape, seed=shape[0], kind="steps").astype(np.float32) * 0.7 + 0.3 * random_plane(*shape, seed=3)
+    V = V.astype(np.float32)
+    got = gpu.resample(_t(V), *out).cpu().numpy()
+    ref = R.tensor_resample(V.astype(np.float64), *out)
+    assert np.abs(got - ref).max() <= TOL
