@@ -410,12 +410,15 @@ def main():
         ms_f = timed(fwd, max(5, args.steps // 10), 3, torch)
         ms_fb = timed(fwdbwd, max(5, args.steps // 10), 3, torch)
         ms_fbl = timed(fwdbwd_loop, max(5, args.steps // 10), 3, torch)
+        gx_batch = wz.zoom2x_backward(xb, gy)
+        same = all(torch.equal(gx_batch[i], wz.zoom2x_backward(xb[i], gy[i])) for i in range(16))
         opx = 16 * 1024 * 1024
         extras["fwd_bwd_16x3x512"] = {"ms_fwd": round(ms_f, 4), "ms_fwd_bwd": round(ms_fb, 4),
                                       "ms_fwd_bwd_per_image_loop": round(ms_fbl, 4),
                                       "Mpix_per_s_fwd": round(opx / (ms_f * 1e-3) / 1e6, 1),
                                       "Mpix_per_s_fwd_bwd": round(opx / (ms_fb * 1e-3) / 1e6, 1),
-                                      "Mpix_per_s_fwd_bwd_per_image_loop": round(opx / (ms_fbl * 1e-3) / 1e6, 1)}
+                                      "Mpix_per_s_fwd_bwd_per_image_loop": round(opx / (ms_fbl * 1e-3) / 1e6, 1),
+                                      "gradients_identical_to_loop": same}
         log("fwd %.3f ms, fwd+bwd %.3f ms (per-image loop %.3f ms)" % (ms_f, ms_fb, ms_fbl))
     except wz.WenoError as e:
         extras["fwd_bwd_16x3x512"] = {"error": str(e)}
