@@ -17,7 +17,8 @@ def _t(a, dtype=np.float32):
 
 
 @pytest.mark.parametrize("shape,out", [((9, 11), (17, 5)), ((40, 70), (100, 33)), ((1, 5), (3, 9)), ((64, 64), (64, 64)),
-                                       ((130, 97), (257, 401)), ((50, 3), (7, 2))])
+                                       ((130, 97), (257, 401)), ((50, 3), (7, 2)), ((7, 1), (13, 4)), ((1, 1), (3, 5)),
+                                       ((6, 2), (1, 1))])
 @pytest.mark.parametrize("beta", [2.0, 1.0])
 def test_resample_f32(gpu, shape, out, beta):
     V = random_plane(*shape, seed=shape[0], kind="steps") * 0.6 + 0.4 * random_plane(*shape, seed=1)
