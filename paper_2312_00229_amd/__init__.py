@@ -223,11 +223,24 @@ def _ws_call(fn_ws, fn, what, x, out, params, workspace):
     return out
 
 
+def _check_out(out, x, out_h, out_w, out_dtype):
+    want = list(x.shape[:-2]) + [int(out_h), int(out_w)]
+    if list(out.shape) != want:
+        raise ValueError("out has shape %s, expected %s" % (tuple(out.shape), tuple(want)))
+    if out_dtype is not None and out.dtype != out_dtype:
+        raise ValueError("out has dtype %s, expected %s" % (out.dtype, out_dtype))
+    return out
+
+
 def resample(x: torch.Tensor, out_h: int, out_w: int, params: Params | None = None, out_dtype=None,
-             workspace: torch.Tensor | None = None) -> torch.Tensor:
+             workspace: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Tensor-product WENO resampling of every (H, W) plane to (out_h, out_w)
-    (eq. tensor), end points aligned."""
-    out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
+    (eq. tensor), end points aligned.  `out` (optional): the caller's output
+    tensor, any strides; `workspace` (optional): resample_workspace_bytes()."""
+    if out is None:
+        out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
+    else:
+        _check_out(out, x, out_h, out_w, out_dtype)
     L = _lib.lib()
     return _ws_call(L.weno_resample_workspace, L.weno_resample, "weno_resample", x, out, params, workspace)
 
@@ -249,10 +262,14 @@ def zoom_to_workspace_bytes(x: torch.Tensor, out_h: int, out_w: int, out_dtype=N
 
 
 def zoom_to(x: torch.Tensor, out_h: int, out_w: int, params: Params | None = None, out_dtype=None,
-            workspace: torch.Tensor | None = None) -> torch.Tensor:
+            workspace: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Zoom to any size (Section 3.3): WD-WENO doublings to the first nested
-    grid at least as large, then tensor-WENO resampling."""
-    out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
+    grid at least as large, then tensor-WENO resampling.  `out` and
+    `workspace` (zoom_to_workspace_bytes()) as for resample."""
+    if out is None:
+        out = _sized_like_layout(x, out_h, out_w, out_dtype or x.dtype)
+    else:
+        _check_out(out, x, out_h, out_w, out_dtype)
     L = _lib.lib()
     return _ws_call(L.weno_zoom_to_workspace, L.weno_zoom_to, "weno_zoom_to", x, out, params, workspace)
 

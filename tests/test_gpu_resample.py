@@ -152,3 +152,23 @@ def test_resample_row_window_steps(gpu, shape, out):
     got = gpu.resample(_t(V), *out).cpu().numpy()
     ref = R.tensor_resample(V.astype(np.float64), *out)
     assert np.abs(got - ref).max() <= TOL
+
+
+def test_caller_output_and_workspace(gpu):
+    # caller-owned output (here an HWC view) and workspace: same result as
+    # the allocating call, and repeated calls reuse them
+    V = random_plane(30, 44, seed=2, kind="steps").astype(np.float32)
+    x = _t(np.stack([V, V * 0.5, 1.0 - V]))
+    ref = gpu.resample(x, 47, 61)
+    out = torch.empty((47, 61, 3), device="cuda").permute(2, 0, 1)
+    ws = torch.empty(gpu.resample_workspace_bytes(x, 47, 61), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        out.fill_(float("nan"))
+        assert gpu.resample(x, 47, 61, workspace=ws, out=out) is out
+        assert torch.equal(out, ref)
+    ref2 = gpu.zoom_to(x, 100, 150)
+    out2 = torch.empty_like(ref2)
+    ws2 = torch.empty(gpu.zoom_to_workspace_bytes(x, 100, 150), dtype=torch.uint8, device="cuda")
+    assert torch.equal(gpu.zoom_to(x, 100, 150, workspace=ws2, out=out2), ref2)
+    with pytest.raises(ValueError):
+        gpu.resample(x, 47, 61, out=torch.empty((3, 47, 60), device="cuda"))
