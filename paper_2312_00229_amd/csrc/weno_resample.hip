@@ -309,8 +309,9 @@ struct FusedArgs {
 };
 
 template <int BETA, int M, bool IN_U8, bool OUT_U8>
-__global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs a, const SamplePos* __restrict__ prow,
-                                                             const SamplePos* __restrict__ pcol)
+__global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs a,
+                                                                      const SamplePos* __restrict__ prow,
+                                                                      const SamplePos* __restrict__ pcol)
 {
     __shared__ float row_buf[2][kFuseThreads * M];
     const int tid = threadIdx.x;
@@ -364,9 +365,9 @@ __global__ __launch_bounds__(kFuseThreads) void fused_resample_kernel(FusedArgs 
     // about 1.33 loads per output row when downsampling by 4/3, against four.
     raw W[M][4];
     int cur = 0;
-    auto row_off = [&](int k) { return (uint32_t)min(max(k, 0), a.in_h - 1) * a.s_h; };
-    auto ld_row = [&](int slot, int k) {
-        const uint32_t so = row_off(k);
+    auto row_off = [&](int row) { return (uint32_t)min(max(row, 0), a.in_h - 1) * a.s_h; };
+    auto ld_row = [&](int slot, int row) {
+        const uint32_t so = row_off(row);
 #pragma unroll
         for (int m = 0; m < M; ++m) W[m][slot] = ld(vin[m], so);
     };
