@@ -40,6 +40,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "weno_fwd.h"
 
 namespace wz {
@@ -106,6 +108,17 @@ __host__ __device__ inline void bwd_strip_span(int W, int sx, int& c0, int& widt
 // rows -4..-1 onto row 0, so it starts 4 rows earlier.
 constexpr int kBwdWarm = 14;
 constexpr int kBwdWarmTop = 18;
+// The first 9 iterations of a walk from row a run the forward pipeline only.
+// Their adjoint work would reach dL/dV rows before a+14 alone: the seeds of
+// A(a+9) enter the indicator adjoint of B(a+10), which feeds dL/dx row a+11,
+// whose phase-1 seed couples into x row a+12 and so into dL/dV row a+14; the
+// seeds of row a+8 and earlier stop at dL/dV row a+13.  (Checked bit for bit
+// against the full walk on strip heights 4..40, beta 1, 1.5 and 2: a tenth
+// forward-only iteration changes the stored rows.)  Forward-only iterations
+// cost about a third of a full one.
+constexpr int kBwdForwardOnly = 9;
+// warm-up cost of a strip in full-iteration equivalents, for the launch model
+constexpr int kBwdWarmCost = kBwdWarm - (2 * kBwdForwardOnly) / 3;
 
 struct BwdCtx {
     rsrc_t x, gy, gx;           // one plane each: forward input, dL/dU (2H x 2W), dL/dV (H x W); float32
@@ -229,17 +242,22 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     int s = R0 - (top ? kBwdWarmTop : kBwdWarm);
     // loads run ahead of their use: V two rows, dL/dU one step
     float Q0 = ldV(s + 5), Q1 = ldV(s + 6);
-    float nA = ldG(2 * s + 1, gyoffA), nB = ldG(2 * s, gyoffB);             // + point seeds of row s
-    float nX = ldG(2 * s - 3, gyoffB), nV = ldG(2 * s - 8, gyoffA);         // x row s-2, V row s-4
-    auto step = [&](const int s) {
+    float nA = 0, nB = 0, nX = 0, nV = 0;
+    // FULL = false: the first kBwdForwardOnly iterations only fill the forward
+    // pipeline; their adjoint work would reach only rows before R0
+    auto step = [&](const int s, auto full) {
+        constexpr bool FULL = decltype(full)::value;
         const float V5 = Q0;
         Q0 = Q1;
         Q1 = ldV(s + 7);
-        const float gA = nA, gB = nB, gXu = nX, gVu = nV;
-        nA = ldG(2 * s + 3, gyoffA);
-        nB = ldG(2 * s + 2, gyoffB);
-        nX = ldG(2 * s - 1, gyoffB);
-        nV = ldG(2 * s - 6, gyoffA);
+        float gA = 0, gB = 0, gXu = 0, gVu = 0;
+        if constexpr (FULL) {
+            gA = nA; gB = nB; gXu = nX; gVu = nV;
+            nA = ldG(2 * s + 3, gyoffA);
+            nB = ldG(2 * s + 2, gyoffB);
+            nX = ldG(2 * s - 1, gyoffB);
+            nV = ldG(2 * s - 6, gyoffA);
+        }
         // ======================= forward =======================
         const float dd1_4 = d2(nbL(V3), V4, nbR(V5));
         const float dd2_4 = d2(nbR(V3), V4, nbL(V5));
@@ -302,8 +320,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             }
         }
         // blends of A(s), B(s) with seed factors
-        float omA[4], dkA[4], omB[4], dkB[4];
-        {
+        float omA[4] = {}, dkA[4] = {}, omB[4] = {}, dkB[4] = {};
+        if constexpr (FULL) {
             float ta[4], tb[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -315,7 +333,10 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= phase-2 seeds =======================
-        float gtA[4], gpA[4], gtB[4], gpB[4], qA[4], qB[4];
+        float gtA[4] = {}, gpA[4] = {}, gtB[4] = {}, gpB[4] = {}, qA[4] = {}, qB[4] = {};
+        float accX_p1 = 0.0f, accV_p1 = 0.0f;
+        float gtX_m2[4] = {}, gpX_m2[4] = {};
+        if constexpr (FULL) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             gpA[k] = gA * omA[k];
@@ -330,7 +351,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= phase-2 adjoint =======================
-        float accX_p1 = 0.0f, accV_p1 = 0.0f;
         {
             // A(s-1): indicator seeds gS = gt_A(s-1) + w [gt_B box over rows s-1, s, cols J-1, J]
             float ga[4], gb[4], gc[4];
@@ -372,7 +392,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
 
         // ======================= phase-1 seeds at x row s-2 =======================
         const float gXc = accX_m2 + gXu;
-        float gtX_m2[4], gpX_m2[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             gpX_m2[k] = gXc * omX[0][k];
@@ -431,6 +450,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
                 if (own) stG(r, val);
             }
         }
+        }   // FULL
 
         // ======================= slide the windows =======================
         Vm4 = Vm3; Vm3 = Vm2; Vm2 = Vm1; Vm1 = V0;
@@ -451,12 +471,24 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         accX_m2 = accX_m1; accX_m1 = accX_0; accX_0 = accX_p1;
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
     };
+    using Fwd = std::integral_constant<bool, false>;
+    using Full = std::integral_constant<bool, true>;
+    const int s_full = min(s + kBwdForwardOnly, s_end + 1);
+    for (; s + 1 < s_full; s += 2) {
+        step(s, Fwd{});
+        step(s + 1, Fwd{});
+    }
+    if (s < s_full) step(s++, Fwd{});
+    nA = ldG(2 * s + 1, gyoffA);   // + point seeds of row s
+    nB = ldG(2 * s, gyoffB);
+    nX = ldG(2 * s - 3, gyoffB);   // x row s-2
+    nV = ldG(2 * s - 8, gyoffA);   // V row s-4
     // two rows per trip so that values carried one row are renamed rather than copied
     for (; s + 1 <= s_end; s += 2) {
-        step(s);
-        step(s + 1);
+        step(s, Full{});
+        step(s + 1, Full{});
     }
-    if (s <= s_end) step(s);
+    if (s <= s_end) step(s, Full{});
     if (bottom) {
         const int r = H - 1;
         if (r >= R0 && own) stG(r, held);

@@ -65,9 +65,10 @@ int64_t bwd_resident_blocks()
     return v;
 }
 
-// Strip height of the adjoint.  Every strip walks rows + kBwdWarm steps and
-// all strips take the same time, so a launch costs about
-//   (rounds of resident blocks) x (rows + kBwdWarm);
+// Strip height of the adjoint.  Every strip walks rows + kBwdWarm steps, the
+// first of them forward only, and all strips take the same time, so a launch
+// costs about
+//   (rounds of resident blocks) x (rows + kBwdWarmCost);
 // the band count that minimises it wins (the fewest bands on a tie).  The
 // best launches fill the device just short of a whole number of rounds with
 // the tallest strips that allows.
@@ -83,7 +84,7 @@ int bwd_auto_rows(int H, int strips_x, int64_t planes, int64_t resident)
         if (bands != b) continue;   // same strips as a smaller band count
         const int64_t blocks = planes * (((int64_t)strips_x * bands + kWavesPerBlock - 1) / kWavesPerBlock);
         const int64_t rounds = (blocks + resident - 1) / resident;
-        const int64_t cost = rounds * (rows + kBwdWarm);
+        const int64_t cost = rounds * (rows + kBwdWarmCost);
         if (cost < best) {
             best = cost;
             best_rows = rows;
