@@ -13,6 +13,7 @@ dtype uint8 or float32, with any strides -- an HWC image is passed as
 from __future__ import annotations
 
 import ctypes
+import functools
 from dataclasses import dataclass
 
 import torch
@@ -55,11 +56,18 @@ class Params:
     # -4 .. W+4 around it are read as they are (zoom2x and batched only)
     boundary: str = "clamp"
 
-    def c(self) -> WenoParams:
+    def _build(self) -> WenoParams:
         if self.boundary not in _BOUNDARY:
             raise ValueError("boundary must be 'clamp' or 'external' (got %r)" % (self.boundary,))
         return WenoParams(float(self.beta), float(self.k_eps), float(self.h), float(self.nbw),
                           _BOUNDARY[self.boundary])
+
+    def c(self) -> WenoParams:
+        """The C struct; built once per distinct parameter set."""
+        try:
+            return _c_params(self.beta, self.k_eps, self.h, self.nbw, self.boundary)
+        except TypeError:  # unhashable field values
+            return self._build()
 
 
 _DT = {torch.uint8: _lib.WENO_U8, torch.float32: _lib.WENO_F32}
@@ -75,40 +83,61 @@ def _as4d(t: torch.Tensor) -> torch.Tensor:
     raise ValueError("expected a tensor of 2, 3 or 4 dims (.., H, W), got %d" % t.dim())
 
 
+def _dims4(shape, stride):
+    """(n, c, h, w, sn, sc, sh, sw) of a 2-, 3- or 4-dim tensor viewed as
+    (N, C, H, W): missing leading dims get size 1 and the stride torch's
+    unsqueeze(0) would give them (size x stride of the dim after), computed
+    from the tuples without building views, since this runs on every call."""
+    nd = len(shape)
+    if nd == 4:
+        return (*shape, *stride)
+    if nd == 3:
+        c, h, w = shape
+        sc, sh, sw = stride
+        return (1, c, h, w, c * sc, sc, sh, sw)
+    if nd == 2:
+        h, w = shape
+        sh, sw = stride
+        return (1, 1, h, w, h * sh, h * sh, sh, sw)
+    raise ValueError("expected a tensor of 2, 3 or 4 dims (.., H, W), got %d" % nd)
+
+
 def _desc(t: torch.Tensor) -> WenoTensor:
     if not t.is_cuda:
         raise ValueError("tensors must live on the GPU (got %s)" % t.device)
-    if t.dtype not in _DT:
+    dt = _DT.get(t.dtype)
+    if dt is None:
         raise ValueError("dtype must be uint8 or float32 (got %s)" % t.dtype)
-    t4 = _as4d(t)
-    n, c, h, w = t4.shape
-    sn, sc, sh, sw = t4.stride()
-    return WenoTensor(t4.data_ptr(), _DT[t.dtype], n, c, h, w, sn, sc, sh, sw)
+    n, c, h, w, sn, sc, sh, sw = _dims4(t.shape, t.stride())
+    return WenoTensor(t.data_ptr(), dt, n, c, h, w, sn, sc, sh, sw)
+
+
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
 
 
 def _stream(device) -> int:
+    """Handle of torch's current HIP stream on `device` (a cuda device)."""
+    if _raw_stream is not None:
+        return _raw_stream(device.index)
     return torch.cuda.current_stream(device).cuda_stream
+
+
+@functools.lru_cache(maxsize=64)
+def _c_params(beta, k_eps, h, nbw, boundary) -> WenoParams:
+    # read-only once built: the library takes the struct through a const pointer
+    return Params(beta=beta, k_eps=k_eps, h=h, nbw=nbw, boundary=boundary)._build()
 
 
 def _params(params, beta, k_eps, h, nbw, boundary="clamp") -> WenoParams:
     if params is None:
-        params = Params(beta=beta, k_eps=k_eps, h=h, nbw=nbw, boundary=boundary)
+        return _c_params(beta, k_eps, h, nbw, boundary)
     return params.c()
 
 
 def _empty_like_layout(x: torch.Tensor, scale: int, dtype) -> torch.Tensor:
     """Output of shape (..., scale H, scale W) in x's memory layout (planar or
     channels-interleaved)."""
-    shape = list(x.shape)
-    shape[-2] *= scale
-    shape[-1] *= scale
-    if x.dim() >= 3 and x.stride(-3) == 1 and x.shape[-3] > 1:
-        # channels interleaved (HWC / NHWC) viewed as (.., C, H, W)
-        perm_shape = shape[:-3] + [shape[-2], shape[-1], shape[-3]]
-        out = torch.empty(perm_shape, dtype=dtype, device=x.device)
-        nd = out.dim()
-        return out.permute(*range(nd - 3), nd - 1, nd - 3, nd - 2)
-    return torch.empty(shape, dtype=dtype, device=x.device)
+    return _sized_like_layout(x, x.shape[-2] * scale, x.shape[-1] * scale, dtype)
 
 
 def zoom2x_(x: torch.Tensor, out: torch.Tensor, params: Params | None = None, *, beta=2.0, k_eps=1e-8,
@@ -200,13 +229,19 @@ def zoom2x_backward(x: torch.Tensor, grad_y: torch.Tensor, params: Params | None
 
 
 def _sized_like_layout(x: torch.Tensor, out_h: int, out_w: int, dtype) -> torch.Tensor:
+    """Output of shape (..., out_h, out_w) in x's memory layout: planar, or
+    channels interleaved (HWC / NHWC viewed as (.., C, H, W)) when x's channel
+    dim has unit stride; allocated with its final strides in one call."""
     shape = list(x.shape)
     shape[-2], shape[-1] = int(out_h), int(out_w)
-    if x.dim() >= 3 and x.stride(-3) == 1 and x.shape[-3] > 1:
-        perm_shape = shape[:-3] + [shape[-2], shape[-1], shape[-3]]
-        out = torch.empty(perm_shape, dtype=dtype, device=x.device)
-        nd = out.dim()
-        return out.permute(*range(nd - 3), nd - 1, nd - 3, nd - 2)
+    if len(shape) >= 3 and x.stride(-3) == 1 and shape[-3] > 1:
+        c, h, w = shape[-3:]
+        strides = [1, w * c, c]
+        inner = c * h * w
+        for size in reversed(shape[:-3]):
+            strides.insert(0, inner)
+            inner *= size
+        return torch.empty_strided(shape, strides, dtype=dtype, device=x.device)
     return torch.empty(shape, dtype=dtype, device=x.device)
 
 

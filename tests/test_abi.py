@@ -215,3 +215,59 @@ def test_workspace_alignment():
     assert L.weno_zoom_to(c(src), c(r), c(p), 0x400000 + 16, 1 << 20, None) == _lib.WENO_EINVAL
     d3 = _t(ptr=0x800000, h=32, w=40)
     assert L.weno_zoom2x_cascade(c(src), c(d3), 3, c(p), 0x400000 + 16, 1 << 20, None) == _lib.WENO_EINVAL
+
+
+def test_descriptor_dims_match_unsqueezed_views():
+    """The per-call descriptor reads sizes and strides from the tuples; they
+    must equal those of the (N, C, H, W) view torch's unsqueeze builds, for
+    planar, channels-interleaved, sliced, transposed and empty tensors."""
+    import torch
+
+    from paper_2312_00229_amd import _as4d, _dims4
+
+    base = torch.zeros(2, 3, 10, 12)
+    cases = [torch.zeros(5, 7), torch.zeros(5, 7)[:, ::2], torch.zeros(7, 5).t(), torch.zeros(0, 7),
+             torch.zeros(3, 5, 7), torch.zeros(5, 7, 3).permute(2, 0, 1), torch.zeros(0, 5, 7),
+             torch.zeros(3, 5, 7)[1:, 2:, ::3], base, base.permute(0, 2, 3, 1).contiguous().permute(0, 3, 1, 2),
+             base[:, :, 1:9, 2:], torch.zeros(1, 1, 1, 1), torch.zeros(4, 9, 9, 3).permute(0, 3, 1, 2)[::2]]
+    for t in cases:
+        v = _as4d(t)
+        assert _dims4(t.shape, t.stride()) == (*v.shape, *v.stride()), (t.shape, t.stride())
+    with pytest.raises(ValueError):
+        _dims4((2, 2, 2, 2, 2), (16, 8, 4, 2, 1))
+
+
+def test_parameter_structs_are_cached_and_checked():
+    from paper_2312_00229_amd import Params, _params
+
+    a, b = Params(beta=1.5, nbw=0.25).c(), Params(beta=1.5, nbw=0.25).c()
+    assert a is b
+    assert (a.beta, a.k_eps, a.h, a.nbw, a.boundary) == (1.5, pytest.approx(1e-8), 1.0, 0.25, 0)
+    assert Params(boundary="external").c().boundary == _lib.WENO_BOUNDARY_EXTERNAL
+    d = _params(None, 2.0, 1e-8, 1.0, -1.0)
+    assert (d.beta, d.h, d.nbw, d.boundary) == (2.0, 1.0, -1.0, 0)
+    with pytest.raises(ValueError):
+        Params(boundary="wrap").c()
+    with pytest.raises(ValueError):
+        _params(None, 2.0, 1e-8, 1.0, -1.0, "wrap")
+
+
+def test_outputs_keep_the_input_layout():
+    """Outputs allocated by the binding are planar-contiguous for planar
+    inputs and channels-interleaved-contiguous (HWC / NHWC memory) for
+    inputs whose channel dim has unit stride."""
+    import torch
+
+    from paper_2312_00229_amd import _empty_like_layout, _sized_like_layout
+
+    planar = [torch.zeros(5, 7), torch.zeros(3, 5, 7), torch.zeros(2, 3, 5, 7), torch.zeros(5, 7, 1).permute(2, 0, 1)]
+    interleaved = [torch.zeros(5, 7, 3).permute(2, 0, 1), torch.zeros(2, 5, 7, 3).permute(0, 3, 1, 2),
+                   torch.zeros(0, 5, 7, 4).permute(0, 3, 1, 2), torch.zeros(3, 2, 5, 7, 3).permute(0, 1, 4, 2, 3)]
+    for x in planar + interleaved:
+        for out in (_empty_like_layout(x, 2, torch.uint8), _sized_like_layout(x, 3, 1, torch.float32)):
+            assert out.shape[:-2] == x.shape[:-2]
+            if any(x is p for p in planar):
+                assert out.is_contiguous()
+            else:
+                assert out.movedim(-3, -1).is_contiguous()
+        assert _empty_like_layout(x, 2, torch.uint8).shape[-2:] == (2 * x.shape[-2], 2 * x.shape[-1])

@@ -112,6 +112,15 @@ def test_calls_on_a_side_stream(gpu):
     assert torch.isfinite(gx).all()
 
 
+def test_stream_handle_is_torchs_current_stream(gpu):
+    dev = torch.device("cuda", 0)
+    assert gpu._stream(dev) == torch.cuda.current_stream(dev).cuda_stream
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        assert gpu._stream(dev) == s.cuda_stream
+    assert gpu._stream(dev) == torch.cuda.current_stream(dev).cuda_stream
+
+
 def test_concurrent_host_threads(gpu):
     gpu.set_launch_config(0, 0)
     inputs = [torch.tensor(random_plane(60 + 7 * i, 90 + 11 * i, seed=20 + i, kind="steps").astype(np.float32),
