@@ -45,34 +45,45 @@ __global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C,
     bwd_strip<BETA>(cx, P, sx, R0, R1);
 }
 
-// Blocks of the adjoint kernel resident on the whole device at once (its
-// register use allows two waves per SIMD, i.e. two blocks per CU).
-int64_t bwd_resident_blocks()
+// Compute units of the current device and blocks of the adjoint kernel one
+// of them holds at once (its register use allows two waves per SIMD, i.e. two
+// blocks per CU), cached per device.
+struct BwdDevice {
+    int cus, per_cu;
+};
+
+BwdDevice bwd_device()
 {
-    static std::atomic<int> cache[64];
+    static std::atomic<int> cache_cus[64], cache_per_cu[64];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
-    int v = cache[dev].load();
-    if (v == 0) {
-        int cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return {256, 2};
+    int cus = cache_cus[dev].load();
+    if (cus == 0) {
+        int per_cu = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(zoom2x_bwd_kernel<2>),
                                                          kBlock, 0) != hipSuccess || per_cu <= 0)
             per_cu = 1;
-        v = cus * per_cu;
-        cache[dev].store(v);
+        cache_per_cu[dev].store(per_cu);
+        cache_cus[dev].store(cus);
     }
-    return v;
+    int per_cu = cache_per_cu[dev].load();
+    return {cus, per_cu > 0 ? per_cu : 1};
 }
 
 // Strip height of the adjoint.  Every strip walks rows + kBwdWarm steps, the
-// first of them forward only, and all strips take the same time, so a launch
-// costs about
-//   (rounds of resident blocks) x (rows + kBwdWarmCost);
-// the band count that minimises it wins (the fewest bands on a tie).  The
-// best launches fill the device just short of a whole number of rounds with
-// the tallest strips that allows.
-int bwd_auto_rows(int H, int strips_x, int64_t planes, int64_t resident)
+// first of them forward only, and all strips take about the same time.  The
+// blocks spread evenly over the CUs, so the busiest CU holds
+// k = ceil(blocks / CUs) of them and runs them two at a time (one at a time
+// where only one fits); a wave that shares its SIMD with another takes about
+// 1.5x as long per row as a wave alone on it (measured on MI355X: ~1.8 us
+// against ~1.2 us per row), so a launch costs about
+//   (1.5 x shared rounds + lone rounds) x (rows + kBwdWarmCost).
+// The band count that minimises it wins (the fewest bands on a tie).  A
+// launch of just over one block per CU thus pays for the pairs it forms: at
+// 3x256x256 the model picks 5-row strips (234 blocks, all alone, 26 us)
+// over 4-row ones (288 blocks, 32 CUs with two, 36 us).
+int bwd_auto_rows(int H, int strips_x, int64_t planes, BwdDevice dev)
 {
     int best_rows = H;
     int64_t best = INT64_MAX;
@@ -83,8 +94,10 @@ int bwd_auto_rows(int H, int strips_x, int64_t planes, int64_t resident)
         const int bands = (H + rows - 1) / rows;
         if (bands != b) continue;   // same strips as a smaller band count
         const int64_t blocks = planes * (((int64_t)strips_x * bands + kWavesPerBlock - 1) / kWavesPerBlock);
-        const int64_t rounds = (blocks + resident - 1) / resident;
-        const int64_t cost = rounds * (rows + kBwdWarmCost);
+        const int64_t k = (blocks + dev.cus - 1) / dev.cus;
+        const int64_t shared = dev.per_cu >= 2 ? k / 2 : 0;
+        const int64_t alone = k - 2 * shared;
+        const int64_t cost = (3 * shared + 2 * alone) * (rows + kBwdWarmCost);
         if (cost < best) {
             best = cost;
             best_rows = rows;
@@ -153,7 +166,7 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     const FwdParams P = wz_fwd_params(p, 0, 0);
     const int strips_x = bwd_strip_count(x->w);
     const int64_t planes = (int64_t)x->n * x->c;
-    int rows = bwd_auto_rows(x->h, strips_x, planes, bwd_resident_blocks());
+    int rows = bwd_auto_rows(x->h, strips_x, planes, bwd_device());
     const int explicit_rows = g_bwd_rows.load();
     if (explicit_rows > 0) rows = explicit_rows;
     const int strips_y = (x->h + rows - 1) / rows;
