@@ -182,8 +182,15 @@ __device__ __forceinline__ void stencil_adj(float gp, float gs, float g, float d
     gc = __builtin_fmaf(gp, -0.125f, 2.0f * e);
 }
 
+typedef float bwd_f32x4 __attribute__((ext_vector_type(4)));
+
+// LDS of one wave for the x-point seed factors: 4 slots (a row each) x
+// (omega_k, dk_k) x 64 lanes of 4 floats
+constexpr int kBwdRingWords = 4 * 2 * kWave;
+
 template <int BETA>
-__device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
+__device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, int strip_x, int R0, int R1,
+                                          bwd_f32x4* __restrict__ ring)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int H = cx.H, W = cx.W;
@@ -229,8 +236,12 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // stencil geometry (g, dd per direction) of B(s) and A(s-1)
     float geoB_gv = 0, geoB_ddd = 0, geoB_ddu = 0, geoB_gh = 0, geoB_ddr = 0, geoB_ddl = 0;
     float geoA_gv = 0, geoA_ddd = 0, geoA_ddu = 0, geoA_gh = 0, geoA_ddr = 0, geoA_ddl = 0;
-    // phase-1 seed factors of x rows s-2 .. s+1
-    float omX[4][4] = {}, dkX[4][4] = {};
+    // The seed factors of x row s+2 (omega_k and omega_k (p_k - u) / t_k),
+    // made at step s, are used at step s+4.  They wait in LDS rather than in
+    // registers: slot s & 3 holds them from step s until step s+4 reads it
+    // and then overwrites it with its own (each lane reads and writes only its
+    // own words, so program order is all the ordering needed).
+    auto ring_at = [&](int s, int half) -> bwd_f32x4& { return ring[((s & 3) * 2 + half) * kWave + lane]; };
     // ---------------- adjoint state ----------------
     float gtA_m1[4] = {}, gpA_m1[4] = {}, qA_m1[4] = {}, qB_m1[4] = {};
     float accX_m2 = 0, accX_m1 = 0, accX_0 = 0;          // dL/dx rows s-2, s-1, s
@@ -251,7 +262,10 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         Q0 = Q1;
         Q1 = ldV(s + 7);
         float gA = 0, gB = 0, gXu = 0, gVu = 0;
+        bwd_f32x4 omXr = {}, dkXr = {};   // seed factors of x row s-2
         if constexpr (FULL) {
+            omXr = ring_at(s, 0);
+            dkXr = ring_at(s, 1);
             gA = nA; gB = nB; gXu = nX; gVu = nV;
             nA = ldG(2 * s + 3, gyoffA);
             nB = ldG(2 * s + 2, gyoffB);
@@ -283,6 +297,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
                 t[k] = __builtin_fmaf(w, ns, SX2[k]);
             }
             X2 = blend_seed<BETA>(t, PX2, beta, omX2, dkX2);
+            ring_at(s, 0) = bwd_f32x4{omX2[0], omX2[1], omX2[2], omX2[3]};
+            ring_at(s, 1) = bwd_f32x4{dkX2[0], dkX2[1], dkX2[2], dkX2[3]};
         }
         const float ddXv1 = d2(X0, X1, X2);
         const float ddr1 = d2(V0, V1, V2);
@@ -337,12 +353,14 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         float accX_p1 = 0.0f, accV_p1 = 0.0f;
         float gtX_m2[4] = {}, gpX_m2[4] = {};
         if constexpr (FULL) {
+        // -beta folds into the seed first (exact for beta = 1 and 2)
+        const float gAb = -beta * gA, gBb = -beta * gB;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             gpA[k] = gA * omA[k];
-            gtA[k] = -beta * (gA * dkA[k]);
+            gtA[k] = gAb * dkA[k];
             gpB[k] = gB * omB[k];
-            gtB[k] = -beta * (gB * dkB[k]);
+            gtB[k] = gBb * dkB[k];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -391,11 +409,11 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= phase-1 seeds at x row s-2 =======================
-        const float gXc = accX_m2 + gXu;
+        const float gXc = accX_m2 + gXu, gXb = -beta * gXc;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            gpX_m2[k] = gXc * omX[0][k];
-            gtX_m2[k] = -beta * (gXc * dkX[0][k]);
+            gpX_m2[k] = gXc * omXr[k];
+            gtX_m2[k] = gXb * dkXr[k];
         }
 
         // ======================= phase-1 adjoint at x row r = s-3 =======================
@@ -461,8 +479,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         for (int k = 0; k < 4; ++k) {
             SX1[k] = SX2[k]; SX2[k] = SX3[k]; PX2[k] = PX3[k];
             SB0[k] = SB1[k]; PB0[k] = PB1[k]; hB0[k] = hB1[k]; hAm1[k] = hA0[k];
-            omX[0][k] = omX[1][k]; omX[1][k] = omX[2][k]; omX[2][k] = omX[3][k]; omX[3][k] = omX2[k];
-            dkX[0][k] = dkX[1][k]; dkX[1][k] = dkX[2][k]; dkX[2][k] = dkX[3][k]; dkX[3][k] = dkX2[k];
             gtA_m1[k] = gtA[k]; gpA_m1[k] = gpA[k]; qA_m1[k] = qA[k]; qB_m1[k] = qB[k];
             gtX_m4[k] = gtX_m3[k]; gtX_m3[k] = gtX_m2[k]; gpX_m3[k] = gpX_m2[k];
         }
@@ -483,12 +499,15 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     nB = ldG(2 * s, gyoffB);
     nX = ldG(2 * s - 3, gyoffB);   // x row s-2
     nV = ldG(2 * s - 8, gyoffA);   // V row s-4
-    // two rows per trip so that values carried one row are renamed rather than copied
-    for (; s + 1 <= s_end; s += 2) {
+    // four rows per trip so that values carried up to four rows are renamed
+    // rather than copied
+    for (; s + 3 <= s_end; s += 4) {
         step(s, Full{});
         step(s + 1, Full{});
+        step(s + 2, Full{});
+        step(s + 3, Full{});
     }
-    if (s <= s_end) step(s, Full{});
+    for (; s <= s_end; ++s) step(s, Full{});
     if (bottom) {
         const int r = H - 1;
         if (r >= R0 && own) stG(r, held);

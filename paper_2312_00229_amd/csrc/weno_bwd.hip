@@ -28,6 +28,7 @@ __global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C,
                                                             int64_t gy_n, int64_t gy_c, int64_t gx_n, int64_t gx_c,
                                                             int strips_x, int strips_y, int rows, FwdParams P)
 {
+    __shared__ bwd_f32x4 ring[kWavesPerBlock * kBwdRingWords];
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     if (wave >= strips_x * strips_y) return;  // whole wave
     const int plane = blockIdx.y;
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C,
     cx.H = base.H; cx.W = base.W;
     const int R0 = sy * rows;
     const int R1 = min(R0 + rows, cx.H);
-    bwd_strip<BETA>(cx, P, sx, R0, R1);
+    bwd_strip<BETA>(cx, P, sx, R0, R1, ring + (threadIdx.x >> 6) * kBwdRingWords);
 }
 
 // Compute units of the current device and blocks of the adjoint kernel one
