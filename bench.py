@@ -187,6 +187,31 @@ def zoom_to_extra(wz, torch, x, dev, steps):
             "resample_stage_algorithmic_bytes": rs_bytes}
 
 
+def fwd_bwd_batch(torch, dev):
+    """The differentiation workload: 16 polygon scenes of 3x512x512 float32
+    (seeds 100..115), a standard-normal dL/dU and the forward's output."""
+    from workloads import scene_rgb, to_planar_f32
+
+    xb = torch.tensor(np.stack([to_planar_f32(scene_rgb(512, 512, seed=100 + i, n_polygons=20))
+                                for i in range(16)]), device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    gy = torch.randn((16, 3, 1024, 1024), device=dev, generator=gen)
+    return xb, gy, torch.empty_like(gy)
+
+
+def only_fwd_bwd(wz, torch, dev, steps, warmup):
+    xb, gy, yb = fwd_bwd_batch(torch, dev)
+
+    def fwdbwd():
+        wz.zoom2x_(xb, yb)
+        wz.zoom2x_backward(xb, gy)
+
+    ms = timed(fwdbwd, steps, warmup, torch)
+    return {"workload": "forward + adjoint, 16x3x512x512 float32", "ms_fwd_bwd": round(ms, 4),
+            "Mpix_per_s_fwd_bwd": round(16 * 1024 * 1024 / (ms * 1e-3) / 1e6, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +223,8 @@ def main():
     ap.add_argument("--only-main", action="store_true", help="time only the headline kernel (for profilers)")
     ap.add_argument("--only-zoom-to", action="store_true",
                     help="time only zoom_to 1080p -> 5760x3240 and its resampler (for profilers)")
+    ap.add_argument("--only-fwd-bwd", action="store_true",
+                    help="time only forward + adjoint of the 16x3x512^2 float32 batch (for profilers)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
@@ -222,6 +249,9 @@ def main():
     planar = to_planar_f32(img)
     x = torch.tensor(planar, device=dev)
     y = torch.empty((3, 2 * H, 2 * W), dtype=torch.float32, device=dev)
+    if args.only_fwd_bwd:
+        print(json.dumps(only_fwd_bwd(wz, torch, dev, args.steps, min(args.warmup, 300))), flush=True)
+        return
     if args.only_zoom_to:
         if args.copy_calib:
             copy_calibration(torch, dev)
@@ -390,10 +420,7 @@ def main():
 
     # ---------------- forward + backward, 16 x 3 x 512 x 512 ----------------
     try:
-        xb = torch.tensor(np.stack([to_planar_f32(scene_rgb(512, 512, seed=100 + i, n_polygons=20))
-                                    for i in range(16)]), device=dev)
-        gy = torch.randn((16, 3, 1024, 1024), device=dev)
-        yb = torch.empty_like(gy)
+        xb, gy, yb = fwd_bwd_batch(torch, dev)
 
         def fwd():
             wz.zoom2x_(xb, yb)
