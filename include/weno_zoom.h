@@ -35,6 +35,10 @@
  *     error, text from weno_status_string) and never aborts.  Argument
  *     errors are detected on the host before anything is enqueued.
  *   - Non-finite inputs propagate; they are not checked.
+ *   - Float samples are supported up to 1e8 in magnitude: the kernels square
+ *     sums of squared differences in FP32 (the doubling's weights 1/t^2, the
+ *     resampler's E0^2 / (E0^2 + k E1^2)), which leave the FP32 range for
+ *     samples of about 1e9 and beyond.
  *   - Thread safety: calls may come from several host threads; the only
  *     process-global state is the launch configuration set by
  *     weno_set_launch_config (read at each call).

@@ -52,11 +52,17 @@ __device__ __forceinline__ float blend(float vm, float v0, float v1, float v2, f
     const float p1 = __builtin_fmaf(hs, __builtin_fmaf(s, B2, B1), v1);
     const float E0 = __builtin_fmaf(A2, __builtin_fmaf(A2, 16.0f / 3.0f, A1 + A1), __builtin_fmaf(A1, A1, eps4));
     const float E1 = __builtin_fmaf(B2, __builtin_fmaf(B2, 16.0f / 3.0f, -(B1 + B1)), __builtin_fmaf(B1, B1, eps4));
-    const float q = E1 * rcp(E0);
-    float g;
-    if constexpr (BETA == 2) g = q * q;
-    else g = __builtin_amdgcn_exp2f(beta * __builtin_amdgcn_logf(q));
-    const float w1 = rcp(__builtin_fmaf(k, g, 1.0f)) * wmask;
+    float w1;
+    if constexpr (BETA == 2) {
+        // 1/(1 + k (E1/E0)^2) = E0^2 / (E0^2 + k E1^2): one reciprocal (the
+        // denominator is at least (4 eps)^2; E^2 stays finite for samples
+        // below ~4e9 in magnitude)
+        const float e0 = E0 * E0;
+        w1 = (e0 * wmask) * rcp(__builtin_fmaf(k, E1 * E1, e0));
+    } else {
+        const float g = __builtin_amdgcn_exp2f(beta * __builtin_amdgcn_logf(E1 * rcp(E0)));
+        w1 = rcp(__builtin_fmaf(k, g, 1.0f)) * wmask;
+    }
     return __builtin_fmaf(w1, p1 - p0, p0);
 }
 
