@@ -350,7 +350,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
 
         // ======================= phase-2 seeds =======================
         float gtA[4] = {}, gpA[4] = {}, gtB[4] = {}, gpB[4] = {}, qA[4] = {}, qB[4] = {};
-        float accX_p1 = 0.0f, accV_p1 = 0.0f;
+        // accumulators start at -0: -0 + x is x for every x, so the first sum is free
+        float accX_p1 = -0.0f, accV_p1 = -0.0f;
         float gtX_m2[4] = {}, gpX_m2[4] = {};
         if constexpr (FULL) {
         // -beta folds into the seed first (exact for beta = 1 and 2)
@@ -447,13 +448,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             float val = accV_m4 + gVu;
             // clamped columns: padded columns -4..-1 fold onto column 0, W..W+3 onto W-1
             if (first_strip) {
-                float p = J < 0 ? val : 0.0f, acc = 0.0f;
+                float p = J < 0 ? val : 0.0f, acc = -0.0f;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { p = nbL(p); acc += p; }
                 if (J == 0) val += acc;
             }
             if (last_strip) {
-                float q = J >= W ? val : 0.0f, acc = 0.0f;
+                float q = J >= W ? val : 0.0f, acc = -0.0f;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { q = nbR(q); acc += q; }
                 if (J == W - 1) val += acc;
