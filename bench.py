@@ -34,6 +34,7 @@ HBM_PEAK_GBPS = 8000.0
 # FP32 VALU peak without packed math (the library is compiled with packed FP32 off):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6432
+ALU_PEAK_PACKED_TFLOPS = 157.2864
 # algorithmic FP32 operations per output quad per channel (FMA = 2, rcp = 1):
 # x point 74, each + point 64, second differences of phase 2 12
 FLOPS_PER_QUAD = 214
@@ -292,6 +293,10 @@ def main():
             "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
             "traffic": traffic,
             "algorithmic_flops_per_launch": alg_flops,
+            # the part's FP32 vector peak counting packed (two-wide) FP32 instructions,
+            # which the library does not use
+            "peak_with_packed_fp32": ALU_PEAK_PACKED_TFLOPS,
+            "frac_of_packed_peak": round(tflops / ALU_PEAK_PACKED_TFLOPS, 4),
         },
         "hbm_roofline": {
             "achieved": round(achieved, 1),
