@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--only-main", action="store_true", help="time only the headline kernel (for profilers)")
     ap.add_argument("--only-zoom-to", action="store_true",
                     help="time only zoom_to 1080p -> 5760x3240 and its resampler (for profilers)")
+    ap.add_argument("--only-u8", action="store_true",
+                    help="time only the same 1080p frame as uint8 HWC -> uint8 HWC (for profilers)")
     ap.add_argument("--only-fwd-bwd", action="store_true",
                     help="time only forward + adjoint of the 16x3x512^2 float32 batch (for profilers)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -250,6 +252,15 @@ def main():
     planar = to_planar_f32(img)
     x = torch.tensor(planar, device=dev)
     y = torch.empty((3, 2 * H, 2 * W), dtype=torch.float32, device=dev)
+    if args.only_u8:
+        if args.copy_calib:
+            copy_calibration(torch, dev)
+        x8 = torch.tensor(img, device=dev).permute(2, 0, 1)
+        y8 = torch.empty((2 * H, 2 * W, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1)
+        ms8 = timed(lambda: wz.zoom2x_(x8, y8), args.steps, args.warmup, torch)
+        print(json.dumps({"workload": "zoom2x 1920x1080 RGB uint8 HWC -> 3840x2160 uint8 HWC", "ms": round(ms8, 5),
+                          "Mpix_per_s": round(4 * H * W / (ms8 * 1e-3) / 1e6, 1)}), flush=True)
+        return
     if args.only_fwd_bwd:
         print(json.dumps(only_fwd_bwd(wz, torch, dev, args.steps, min(args.warmup, 300))), flush=True)
         return

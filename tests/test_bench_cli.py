@@ -22,5 +22,6 @@ def test_more_than_one_gpu_is_refused():
 def test_profiling_modes_are_listed():
     r = _run("--help")
     assert r.returncode == 0
-    for flag in ("--steps", "--warmup", "--only-main", "--only-zoom-to", "--only-fwd-bwd", "--copy-calib", "--no-cpu"):
+    for flag in ("--steps", "--warmup", "--only-main", "--only-zoom-to", "--only-fwd-bwd", "--only-u8", "--copy-calib",
+                 "--no-cpu"):
         assert flag in r.stdout, flag
