@@ -20,13 +20,14 @@
 // lanes, with no atomics: each dL/dV element is written by exactly one lane,
 // and the result is deterministic.  Iteration s:
 //   forward     the forward pipeline (rows up to s+5), blends of A(s), B(s)
-//               and x(s+2) keep the weight factors the seeds need;
+//               and x(s+2) keep the weight factors the seeds need (those of
+//               x(s+2) wait in LDS until iteration s+4);
 //   seeds       phase-2 seeds of A(s), B(s) from dL/dU;
 //   p2 adjoint  indicator adjoints of A(s-1) and B(s); stencil adjoints into
 //               dL/dx (rows s-2..s+1) and dL/dV (rows s-2..s+1);
 //   p1 seeds    dL/dx of row s-2 is complete: seeds of x(s-2);
 //   p1 adjoint  indicator adjoints of x(s-3); stencil adjoints into dL/dV
-//               rows s-4..s-1 (input rows reloaded from memory);
+//               rows s-4..s-1 (input rows s-4..s-1 held in a register window);
 //   output      dL/dV row s-4 is complete: fold clamped rows/columns onto the
 //               edge pixels and store.
 // Valid lanes shrink with every neighbour access: the dL/dV of lanes 9..54 is
