@@ -36,10 +36,11 @@ namespace {
 //   4 (eps + SI_1) = E_1 = 4 eps + B1^2 - 2 B1 B2 + (16/3) B2^2,
 // and, dividing alpha_0 + alpha_1 by alpha_1,
 //   omega_1 = 1 / (1 + (C_0/C_1) (E_1/E_0)^beta),   u = p_i + omega_1 (p_{i+1} - p_i),
-// two reciprocals per sample.  E_0, E_1 >= 4 eps > 0 (for beta = 0 the host
+// for beta = 2 written E_0^2 / (E_0^2 + k E_1^2) with one reciprocal per
+// sample (two for other beta).  E_0, E_1 >= 4 eps > 0 (for beta = 0 the host
 // passes eps = 1: the weights are then C_s whatever the indicators).  A node
-// (t = 0, wmask = 0) gets omega_1 = 0 (1/(1 + k g) <= 1 is finite), so
-// u = p_i = v_i exactly.
+// (t = 0, wmask = 0) gets omega_1 = 0 (the reciprocal is of a positive finite
+// number), so u = p_i = v_i exactly.
 template <int BETA>
 __device__ __forceinline__ float blend(float vm, float v0, float v1, float v2, float t, float s, float ht, float hs,
                                        float k, float eps4, float beta, float wmask = 1.0f)
