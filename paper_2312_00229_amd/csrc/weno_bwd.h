@@ -257,8 +257,11 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     float nA = 0, nB = 0, nX = 0, nV = 0;
     // FULL = false: the first kBwdForwardOnly iterations only fill the forward
     // pipeline; their adjoint work would reach only rows before R0
-    auto step = [&](const int s, auto full) {
+    // P1 = false (full iterations only): skip the phase-1 stencil adjoint and
+    // the output, which reach only rows this strip never stores
+    auto step = [&](const int s, auto full, auto p1) {
         constexpr bool FULL = decltype(full)::value;
+        constexpr bool P1 = decltype(p1)::value;
         const float V5 = Q0;
         Q0 = Q1;
         Q1 = ldV(s + 7);
@@ -419,7 +422,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= phase-1 adjoint at x row r = s-3 =======================
-        {
+        if constexpr (P1) {
             const float Pv = Vm4, Qv = Vm3, Rv = Vm2, Tv = Vm1;
             const float dd1_r = d2(nbL(Pv), Qv, nbR(Rv));
             const float dd1s_r1 = nbR(d2(nbL(Qv), Rv, nbR(Tv)));
@@ -444,7 +447,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }
 
         // ======================= dL/dV row s-4 is complete =======================
-        {
+        if constexpr (P1) {
             const int r = s - 4;
             float val = accV_m4 + gVu;
             // clamped columns: padded columns -4..-1 fold onto column 0, W..W+3 onto W-1
@@ -491,25 +494,37 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     };
     using Fwd = std::integral_constant<bool, false>;
     using Full = std::integral_constant<bool, true>;
+    using No = std::integral_constant<bool, false>;
+    using Yes = std::integral_constant<bool, true>;
     const int s_full = min(s + kBwdForwardOnly, s_end + 1);
     for (; s + 1 < s_full; s += 2) {
-        step(s, Fwd{});
-        step(s + 1, Fwd{});
+        step(s, Fwd{}, No{});
+        step(s + 1, Fwd{}, No{});
     }
-    if (s < s_full) step(s++, Fwd{});
+    if (s < s_full) step(s++, Fwd{}, No{});
     nA = ldG(2 * s + 1, gyoffA);   // + point seeds of row s
     nB = ldG(2 * s, gyoffB);
     nX = ldG(2 * s - 3, gyoffB);   // x row s-2
     nV = ldG(2 * s - 8, gyoffA);   // V row s-4
+    // The phase-1 adjoint of iteration s feeds dL/dV rows s-4 .. s-1, and its
+    // output stores row s-4: until s = R0 + 1 (the top strip: s = -3, for the
+    // folded rows -4 .. -1) both reach only rows this strip never stores, so
+    // those iterations (the 6 after the forward-only ones) skip them.
+    const int s_p1 = min(top ? -3 : R0 + 1, s_end + 1);
+    for (; s + 1 < s_p1; s += 2) {
+        step(s, Full{}, No{});
+        step(s + 1, Full{}, No{});
+    }
+    if (s < s_p1) step(s++, Full{}, No{});
     // four rows per trip so that values carried up to four rows are renamed
     // rather than copied
     for (; s + 3 <= s_end; s += 4) {
-        step(s, Full{});
-        step(s + 1, Full{});
-        step(s + 2, Full{});
-        step(s + 3, Full{});
+        step(s, Full{}, Yes{});
+        step(s + 1, Full{}, Yes{});
+        step(s + 2, Full{}, Yes{});
+        step(s + 3, Full{}, Yes{});
     }
-    for (; s <= s_end; ++s) step(s, Full{});
+    for (; s <= s_end; ++s) step(s, Full{}, Yes{});
     if (bottom) {
         const int r = H - 1;
         if (r >= R0 && own) stG(r, held);
