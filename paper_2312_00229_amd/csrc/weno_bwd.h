@@ -255,12 +255,21 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // loads run ahead of their use: V two rows, dL/dU one step
     float Q0 = ldV(s + 5), Q1 = ldV(s + 6);
     float nA = 0, nB = 0, nX = 0, nV = 0;
-    // FULL = false: the first kBwdForwardOnly iterations only fill the forward
-    // pipeline; their adjoint work would reach only rows before R0
+    // D = 0: a full iteration.  D = -9 .. -1: the forward-only iteration
+    // a + 9 + D of a walk that starts at row a (the first kBwdForwardOnly
+    // iterations only fill the forward pipeline; their adjoint work would
+    // reach only rows before R0).  Like the doubling's prologue, each runs only
+    // the stages whose results reach the first full iteration: second
+    // differences from D = -7, x-point indicators from -6, x-point blends and
+    // their seed factors (read four iterations later) from -4, the vertical
+    // differences of the + points from -2 and the + points from -1.
     // P1 = false (full iterations only): skip the phase-1 stencil adjoint and
     // the output, which reach only rows this strip never stores
-    auto step = [&](const int s, auto full, auto p1) {
-        constexpr bool FULL = decltype(full)::value;
+    auto step = [&](const int s, auto dconst, auto p1) {
+        constexpr int D = decltype(dconst)::value;
+        constexpr bool FULL = D == 0;
+        constexpr bool do_dd = FULL || D >= -7, do_sx = FULL || D >= -6, do_x = FULL || D >= -4;
+        constexpr bool do_p2dd = FULL || D >= -2, do_p2 = FULL || D >= -1;
         constexpr bool P1 = decltype(p1)::value;
         const float V5 = Q0;
         Q0 = Q1;
@@ -277,12 +286,16 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             nV = ldG(2 * s - 6, gyoffA);
         }
         // ======================= forward =======================
-        const float dd1_4 = d2(nbL(V3), V4, nbR(V5));
-        const float dd2_4 = d2(nbR(V3), V4, nbL(V5));
-        const float dd1s_4 = nbR(dd1_4), dd2s_4 = nbR(dd2_4);
+        float dd1_4 = 0.0f, dd2_4 = 0.0f, dd1s_4 = 0.0f, dd2s_4 = 0.0f;
+        if constexpr (do_dd) {
+            dd1_4 = d2(nbL(V3), V4, nbR(V5));
+            dd2_4 = d2(nbR(V3), V4, nbL(V5));
+            dd1s_4 = nbR(dd1_4);
+            dd2s_4 = nbR(dd2_4);
+        }
         // x row s+3
-        float SX3[4], PX3[4];
-        {
+        float SX3[4] = {1, 1, 1, 1}, PX3[4] = {};
+        if constexpr (do_sx) {
             const float a1 = V3, b1 = nbR(V4), a2 = nbR(V3), b2 = V4;
             const float gc1 = gterm(b1 - a1, eh), gc2 = gterm(b2 - a2, eh);
             const float m1 = 0.5f * (a1 + b1), m2 = 0.5f * (a2 + b2);
@@ -292,8 +305,9 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             SX3[3] = sidx(dd2_4, gc2);   PX3[3] = cand(dd2_4, m2);
         }
         // x row s+2 with its seed factors
-        float X2, omX2[4], dkX2[4];
-        {
+        float X2 = 0.0f;
+        if constexpr (do_x) {
+            float omX2[4], dkX2[4];
             float t[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -304,13 +318,17 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             ring_at(s, 0) = bwd_f32x4{omX2[0], omX2[1], omX2[2], omX2[3]};
             ring_at(s, 1) = bwd_f32x4{dkX2[0], dkX2[1], dkX2[2], dkX2[3]};
         }
-        const float ddXv1 = d2(X0, X1, X2);
-        const float ddr1 = d2(V0, V1, V2);
+        float ddXv1 = 0.0f, ddr1 = 0.0f;
+        if constexpr (do_p2dd) {
+            ddXv1 = d2(X0, X1, X2);
+            ddr1 = d2(V0, V1, V2);
+        }
         // + points: B(s+1) and A(s)
-        float SB1[4], PB1[4], hB1[4], SA0[4], PA0[4], hA0[4];
-        float nB_gv, nB_ddd, nB_ddu, nB_gh, nB_ddr, nB_ddl;   // geometry of B(s+1)
-        float nA_gv, nA_ddd, nA_ddu, nA_gh, nA_ddr, nA_ddl;   // geometry of A(s)
-        {
+        float SB1[4] = {1, 1, 1, 1}, PB1[4] = {}, hB1[4] = {1, 1, 1, 1};
+        float SA0[4] = {1, 1, 1, 1}, PA0[4] = {}, hA0[4] = {1, 1, 1, 1};
+        float nB_gv = 0, nB_ddd = 0, nB_ddu = 0, nB_gh = 0, nB_ddr = 0, nB_ddl = 0;   // geometry of B(s+1)
+        float nA_gv = 0, nA_ddd = 0, nA_ddu = 0, nA_gh = 0, nA_ddr = 0, nA_ddl = 0;   // geometry of A(s)
+        if constexpr (do_p2) {
             const float v1r = nbR(V1);
             const float ddc = d2(nbL(V1), V1, v1r);
             const float x0l = nbL(X0);
@@ -492,16 +510,27 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         accX_m2 = accX_m1; accX_m1 = accX_0; accX_0 = accX_p1;
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
     };
-    using Fwd = std::integral_constant<bool, false>;
-    using Full = std::integral_constant<bool, true>;
+    using Full = std::integral_constant<int, 0>;
     using No = std::integral_constant<bool, false>;
     using Yes = std::integral_constant<bool, true>;
-    const int s_full = min(s + kBwdForwardOnly, s_end + 1);
-    for (; s + 1 < s_full; s += 2) {
-        step(s, Fwd{}, No{});
-        step(s + 1, Fwd{}, No{});
+    static_assert(kBwdForwardOnly == 9, "the forward-only iterations are D = -9 .. -1");
+    {
+        const int s0 = s;
+        auto fwd_only = [&](auto dconst) {
+            constexpr int D = decltype(dconst)::value;
+            if (s0 + 9 + D <= s_end) step(s0 + 9 + D, dconst, No{});
+        };
+        fwd_only(std::integral_constant<int, -9>{});
+        fwd_only(std::integral_constant<int, -8>{});
+        fwd_only(std::integral_constant<int, -7>{});
+        fwd_only(std::integral_constant<int, -6>{});
+        fwd_only(std::integral_constant<int, -5>{});
+        fwd_only(std::integral_constant<int, -4>{});
+        fwd_only(std::integral_constant<int, -3>{});
+        fwd_only(std::integral_constant<int, -2>{});
+        fwd_only(std::integral_constant<int, -1>{});
+        s = min(s0 + kBwdForwardOnly, s_end + 1);
     }
-    if (s < s_full) step(s++, Fwd{}, No{});
     nA = ldG(2 * s + 1, gyoffA);   // + point seeds of row s
     nB = ldG(2 * s, gyoffB);
     nX = ldG(2 * s - 3, gyoffB);   // x row s-2
