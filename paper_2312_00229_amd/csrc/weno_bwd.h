@@ -315,8 +315,16 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
                 t[k] = __builtin_fmaf(w, ns, SX2[k]);
             }
             X2 = blend_seed<BETA>(t, PX2, beta, omX2, dkX2);
-            ring_at(s, 0) = bwd_f32x4{omX2[0], omX2[1], omX2[2], omX2[3]};
-            ring_at(s, 1) = bwd_f32x4{dkX2[0], dkX2[1], dkX2[2], dkX2[3]};
+            // The factors written at iteration s feed the phase-1 seeds of x
+            // row s+2 at iteration s+4, which a kept row needs only from the
+            // first full iteration's write on (rows s+2 >= R0-3, or >= -7 for
+            // the top strip); the first four full iterations read slots the
+            // forward-only ones leave unwritten, and their seeds reach only
+            // phase-1 adjoints that are skipped.
+            if constexpr (FULL) {
+                ring_at(s, 0) = bwd_f32x4{omX2[0], omX2[1], omX2[2], omX2[3]};
+                ring_at(s, 1) = bwd_f32x4{dkX2[0], dkX2[1], dkX2[2], dkX2[3]};
+            }
         }
         float ddXv1 = 0.0f, ddr1 = 0.0f;
         if constexpr (do_p2dd) {
