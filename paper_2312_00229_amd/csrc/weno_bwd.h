@@ -116,10 +116,14 @@ constexpr int kBwdWarmTop = 18;
 // seeds of row a+8 and earlier stop at dL/dV row a+13.  (Checked bit for bit
 // against the full walk on strip heights 4..40, beta 1, 1.5 and 2: a tenth
 // forward-only iteration changes the stored rows.)  Forward-only iterations
-// cost about a third of a full one.
+// run only the stages whose results reach the first full iteration.
 constexpr int kBwdForwardOnly = 9;
-// warm-up cost of a strip in full-iteration equivalents, for the launch model
-constexpr int kBwdWarmCost = kBwdWarm - (2 * kBwdForwardOnly) / 3;
+// Warm-up cost of a strip in full-iteration equivalents, for the launch
+// model: the 14 warm-up iterations (9 forward-only with partial stages, then
+// full ones without the phase-1 adjoint) together with the fixed cost of
+// starting a wave.  Fitted on MI355X: 8 picks the best measured strip height
+// on 3x512^2, 1x2048^2, 3x720x1280 and the shapes of the launch-model fit.
+constexpr int kBwdWarmCost = 8;
 
 struct BwdCtx {
     rsrc_t x, gy, gx;           // one plane each: forward input, dL/dU (2H x 2W), dL/dV (H x W); float32
