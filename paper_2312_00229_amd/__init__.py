@@ -218,10 +218,18 @@ def cascade_workspace_bytes(x: torch.Tensor, levels: int) -> int:
     return int(_lib.lib().weno_zoom2x_cascade_workspace(ctypes.byref(s), int(levels)))
 
 
-def zoom2x_backward(x: torch.Tensor, grad_y: torch.Tensor, params: Params | None = None) -> torch.Tensor:
-    """Adjoint of zoom2x for float32 x: returns dL/dx given dL/dy."""
+def zoom2x_backward(x: torch.Tensor, grad_y: torch.Tensor, params: Params | None = None,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """Adjoint of zoom2x for float32 x: returns dL/dx given dL/dy, written
+    into `out` (float32, x's shape, any strides) when given."""
     p = (params or Params()).c()
-    gx = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    if out is None:
+        gx = torch.empty(x.shape, dtype=torch.float32, device=x.device)
+    else:
+        if tuple(out.shape) != tuple(x.shape) or out.dtype != torch.float32:
+            raise ValueError("out must be float32 of shape %s (got %s %s)" % (tuple(x.shape), out.dtype,
+                                                                               tuple(out.shape)))
+        gx = out
     a, g, o = _desc(x), _desc(grad_y), _desc(gx)
     _lib.check(_lib.lib().weno_zoom2x_backward(ctypes.byref(a), ctypes.byref(g), ctypes.byref(o), ctypes.byref(p),
                                                _stream(x.device)), "weno_zoom2x_backward")

@@ -89,6 +89,18 @@ def test_backward_batch_and_strides(gpu):
     assert _close(got2, _ref(V[0], G[0]))
 
 
+def test_backward_into_callers_output(gpu):
+    rng = np.random.default_rng(12)
+    x = _t(rng.random((3, 40, 70)))
+    g = _t(rng.standard_normal((3, 80, 140)))
+    ref = gpu.zoom2x_backward(x, g)
+    out = torch.full((40, 70, 3), float("nan"), device="cuda").permute(2, 0, 1)   # any strides
+    assert gpu.zoom2x_backward(x, g, out=out) is out
+    assert torch.equal(out, ref)
+    with pytest.raises(ValueError):
+        gpu.zoom2x_backward(x, g, out=torch.empty((3, 40, 71), device="cuda"))
+
+
 def test_backward_deterministic(gpu):
     rng = np.random.default_rng(5)
     x = _t(rng.random((3, 100, 150)))
