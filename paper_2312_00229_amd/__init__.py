@@ -197,11 +197,15 @@ def zoom2x_batched(xs, params: Params | None = None, out_dtype=None):
 
 
 def zoom2x_cascade(x: torch.Tensor, levels: int, params: Params | None = None, out_dtype=None,
-                   workspace: torch.Tensor | None = None) -> torch.Tensor:
+                   workspace: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """`levels` successive doublings (eq. zoomfactor) with FP32 intermediates,
-    grid spacing halved per level."""
+    grid spacing halved per level.  `out` (optional): the caller's output
+    tensor, any strides; `workspace` (optional): cascade_workspace_bytes()."""
     p = (params or Params()).c()
-    out = _empty_like_layout(x, 2 ** levels, out_dtype or x.dtype)
+    if out is None:
+        out = _empty_like_layout(x, 2 ** levels, out_dtype or x.dtype)
+    else:
+        _check_out(out, x, x.shape[-2] << levels, x.shape[-1] << levels, out_dtype)
     s, d = _desc(x), _desc(out)
     L = _lib.lib()
     ws = L.weno_zoom2x_cascade_workspace(ctypes.byref(s), int(levels))

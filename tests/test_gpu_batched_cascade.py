@@ -74,3 +74,19 @@ def test_cascade_graph_replay(gpu):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(res, eager)
+
+
+def test_cascade_into_callers_output(gpu):
+    rng = np.random.default_rng(21)
+    x = torch.tensor(rng.integers(0, 256, size=(37, 53, 3), dtype=np.uint8), device="cuda").permute(2, 0, 1)
+    ref = gpu.zoom2x_cascade(x, 2)
+    out = torch.empty((148, 212, 3), dtype=torch.uint8, device="cuda").permute(2, 0, 1)
+    assert gpu.zoom2x_cascade(x, 2, out=out) is out
+    assert torch.equal(out, ref)
+    # planar float32 output of the same cascade
+    ref_f = gpu.zoom2x_cascade(x, 2, out_dtype=torch.float32)
+    out_f = torch.empty((3, 148, 212), dtype=torch.float32, device="cuda")
+    gpu.zoom2x_cascade(x, 2, out=out_f, out_dtype=torch.float32)
+    assert torch.equal(out_f, ref_f)
+    with pytest.raises(ValueError):
+        gpu.zoom2x_cascade(x, 2, out=torch.empty((3, 148, 211), dtype=torch.uint8, device="cuda"))
