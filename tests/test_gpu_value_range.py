@@ -45,3 +45,16 @@ def test_resample_across_magnitudes(gpu, scale, out):
     V = _plane(41, 170, seed=13, scale=scale)
     got = gpu.resample(_f32(V), *out).cpu().numpy()
     assert _close(got, R.tensor_resample(V.astype(np.float64), *out)), (scale, out)
+
+
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 1e4])
+def test_adjoint_across_magnitudes(gpu, scale):
+    """The map is homogeneous of degree one where eps is negligible, so the
+    gradient keeps its magnitude across sample scales; parity with the FP64
+    hand adjoint within 1e-4 of max(1, |ref|)."""
+    V = _plane(29, 90, seed=17, scale=scale)
+    G = np.random.default_rng(17).standard_normal((58, 180)).astype(np.float32)
+    got = gpu.zoom2x_backward(_f32(V), _f32(G)).cpu().numpy()
+    ref = oracle.backward(V.astype(np.float64), G.astype(np.float64))
+    assert np.isfinite(got).all()
+    assert np.abs(got - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max()), scale
