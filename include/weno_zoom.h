@@ -90,14 +90,15 @@ typedef struct {
                      the paper's usual value 1e-8                              */
     float h;      /* input grid spacing (> 0); 1 for images                    */
     float nbw;    /* weight of the four neighbour indicators in D, eqs.
-                     (2DsmoothnessFinal) and (tezine).  < 0 selects the
-                     definitions' h^2/4; the paper's convergence table is
-                     reproduced with h^2/8 (the value in the proof of
-                     Theorem 1), which callers may pass explicitly.           */
+                     (2DsmoothnessFinal) and (tezine).  < 0 selects h^2/8,
+                     the value in the proof of Theorem 1 (eq. DDiffOrder)
+                     and the one that reproduces row 2 of Table 1; the
+                     definitions print h^2/4, which callers may pass
+                     explicitly.                                               */
     int32_t boundary; /* weno_boundary_t                                       */
 } weno_params_t;
 
-/* Default parameters: beta 2, k_eps 1e-8, h 1, nbw -1 (h^2/4), clamp. */
+/* Default parameters: beta 2, k_eps 1e-8, h 1, nbw -1 (h^2/8), clamp. */
 weno_params_t weno_default_params(void);
 
 /*

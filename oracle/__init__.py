@@ -15,7 +15,9 @@ Contents
 Readings of open points (see the header of weno_oracle.c): clamp-to-edge
 padding, one-fine-step direction vectors, interval-length indicator scale
 (`si_mode=0`; `si_mode=1` is the literal sqrt(2)h scale of eq. 2Dsmoothness),
-neighbour weight h^2/4, 2n x 2m output.
+neighbour weight h^2/8 (the proof of Theorem 1; the only printed number that
+separates it from the definitions' h^2/4, Table 1 row 2, selects it), 2n x 2m
+output.
 """
 from __future__ import annotations
 

@@ -17,7 +17,8 @@ geometric definitions instead of closed forms:
     sqrt(2) h with `si_mode=1`);
   * D adds the same-direction indicators of the four neighbours of eq.
     (2DsmoothnessFinal) (phase 1) or eq. (tezine) (phase 2), weighted by
-    `nbw` (h^2/4 unless given);
+    `nbw` (h^2/8 unless given: the proof of Theorem 1 and Table 1 row 2;
+    the definitions print h^2/4);
   * alpha = 0.5 / (eps + D)^beta, eq. (alpha), omega = alpha / sum alpha and
     u = sum omega p, eqs. (IzrazOmega2d) / (2dKombinacija).
 
@@ -58,7 +59,7 @@ class BruteWENO:
         self.beta = float(beta)
         self.h = float(h)
         self.eps = keps * h * h
-        self.nbw = h * h / 4.0 if nbw is None else float(nbw)
+        self.nbw = h * h / 8.0 if nbw is None else float(nbw)
         self.si_mode = si_mode
         self._val = {}
         self._stencil = {}

@@ -41,7 +41,7 @@ def zoom2x(V: torch.Tensor, beta=2.0, keps=1e-8, h=1.0, nbw=None) -> torch.Tenso
     """V: (..., n, m) float64 -> (..., 2n, 2m)."""
     n, m = V.shape[-2:]
     eps = keps * h * h
-    w = h * h / 4.0 if nbw is None else nbw
+    w = h * h / 8.0 if nbw is None else nbw
     ri = torch.arange(-M, n + M).clamp(0, n - 1)
     ci = torch.arange(-M, m + M).clamp(0, m - 1)
     Vp = V.index_select(-2, ri).index_select(-1, ci)  # Vp[..., I+M, J+M]

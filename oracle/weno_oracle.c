@@ -38,8 +38,10 @@ typedef struct {
     double beta;   /* exponent of the nonlinear weights, eq. (alpha)              */
     double keps;   /* K_eps, eps_h = K_eps h^2 (Section 2, eq. IzrazOmega)        */
     double h;      /* coarse (input) grid spacing                                  */
-    double nbw;    /* neighbour-indicator weight; < 0 selects h^2/4 (eqs.
-                      2DsmoothnessFinal and tezine)                                */
+    double nbw;    /* neighbour-indicator weight; < 0 selects h^2/8, the value in
+                      the proof of Theorem 1 (eq. DDiffOrder) that reproduces
+                      Table 1 row 2; eqs. 2DsmoothnessFinal and tezine print
+                      h^2/4, which callers pass explicitly                        */
     int si_mode;   /* 0: interval-length scale, 1: literal sqrt(2)h scale          */
 } weno_oracle_params;
 
@@ -177,7 +179,7 @@ static int st_init(wo_state* s, const double* V, int n, int m, const weno_oracle
     s->m = m;
     s->beta = p->beta;
     s->eps = p->keps * p->h * p->h;
-    s->nbw = p->nbw < 0.0 ? p->h * p->h / 4.0 : p->nbw;
+    s->nbw = p->nbw < 0.0 ? p->h * p->h / 8.0 : p->nbw;
     s->step1 = sqrt(2.0) / 2.0 * p->h;
     s->step2 = p->h / 2.0;
     if (p->si_mode == 1) {

@@ -50,7 +50,7 @@ class Params:
     beta: float = 2.0
     k_eps: float = 1e-8
     h: float = 1.0
-    nbw: float = -1.0  # < 0: h^2 / 4
+    nbw: float = -1.0  # < 0: h^2 / 8
     # "clamp": samples beyond the plane are its edge samples; "external": the
     # input is a view into a larger array whose rows -4 .. H+4 and columns
     # -4 .. W+4 around it are read as they are (zoom2x and batched only)

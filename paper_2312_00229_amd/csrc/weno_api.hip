@@ -245,7 +245,7 @@ int wz_check_params(const weno_params_t* p)
     return WENO_OK;
 }
 
-double wz_nbw(const weno_params_t* p) { return p->nbw < 0.0f ? (double)p->h * (double)p->h / 4.0 : (double)p->nbw; }
+double wz_nbw(const weno_params_t* p) { return p->nbw < 0.0f ? (double)p->h * (double)p->h / 8.0 : (double)p->nbw; }
 
 FwdParams wz_fwd_params(const weno_params_t* p, int in_u8, int out_u8)
 {

@@ -68,7 +68,7 @@ def test_backward_beta0_without_eps(gpu, kind):
     assert _close(got, _ref(V, G, beta=0.0, keps=0.0))
 
 
-@pytest.mark.parametrize("nbw,h", [(0.125, 1.0), (0.0, 1.0), (-1.0, 0.25)])
+@pytest.mark.parametrize("nbw,h", [(0.25, 1.0), (0.0, 1.0), (-1.0, 0.25)])
 def test_backward_parameters(gpu, nbw, h):
     rng = np.random.default_rng(3)
     V = random_plane(20, 50, seed=2, kind="steps") * 0.5 + 0.5 * rng.random((20, 50))

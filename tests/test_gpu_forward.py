@@ -64,7 +64,7 @@ def test_forward_beta0_without_eps(gpu, kind):
     assert np.abs(U - ref).max() <= TOL
 
 
-@pytest.mark.parametrize("nbw,h,keps", [(0.125, 1.0, 1e-8), (0.0, 1.0, 1e-8), (-1.0, 0.5, 1e-6), (-1.0, 2.0, 1e-8)])
+@pytest.mark.parametrize("nbw,h,keps", [(0.25, 1.0, 1e-8), (0.0, 1.0, 1e-8), (-1.0, 0.5, 1e-6), (-1.0, 2.0, 1e-8)])
 def test_forward_parameters(gpu, nbw, h, keps):
     _set(gpu, (64, 2))
     V = random_plane(40, 70, seed=11, kind="steps").astype(np.float32)

@@ -24,7 +24,7 @@ def test_c_oracle_matches_brute_force(oracle_mod, n, m, beta):
 
 
 @pytest.mark.parametrize("si_mode", [0, 1])
-@pytest.mark.parametrize("nbw", [None, 0.125, 0.0])
+@pytest.mark.parametrize("nbw", [None, 0.25, 0.0])
 @pytest.mark.parametrize("kind", ["uniform", "steps", "binary"])
 def test_c_oracle_matches_brute_force_variants(oracle_mod, si_mode, nbw, kind):
     V = random_plane(5, 6, seed=7, kind=kind)

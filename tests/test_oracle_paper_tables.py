@@ -5,13 +5,17 @@ Readings of the paper used here:
     nodes -1 + 2hk, n = 1/h + 1 per side, output (2n-1)^2 points on [-1,1]^2;
   * samples outside [-1,1]^2 are f itself (ghost samples): row 1 of Table 1,
     12/19, comes out only then (clamping gives 2/3);
-  * the neighbour weight that reproduces row 2 of Table 1 is h^2/8 (the value
-    written in the proof of Theorem 1); the definitions print h^2/4, which
-    gives 1.10E-01 instead of 1.33E-01 for row 2;
+  * the neighbour weight is h^2/8 (the value written in the proof of
+    Theorem 1, and the oracle's default): it reproduces row 2 of Table 1 to
+    the printed digits, where the definitions' h^2/4 gives 1.10E-01 instead
+    of 1.33E-01;
   * the indicator scale is the integration-interval length (the literal
     sqrt(2)h scale moves rows 7-10 by 2-4 %, beyond the printed digits);
-  * L2 values differ from ours by a constant factor (norm normalisation not
-    stated), so only the L2 orders are compared.
+  * the L2 column is not reproduced by any normalisation tried (RMS over all
+    points, over the new points only, trapezoid-weighted, x or + points
+    only): the RMS over all points is 1.10-1.12 times the printed value at
+    rows 4-9 and 0.73, 0.89, 1.06 at rows 1-3, so only the L2 orders and
+    that fine-row factor are compared.
 """
 import os
 
@@ -66,14 +70,22 @@ def test_table1_row1_rejects_clamped_boundary(oracle_mod):
     assert abs(abs(U[1, 1] - 1.0) - 2.0 / 3.0) <= 1e-12
 
 
+# Relative band per row of Table 1's L_inf column.  Rows 1, 2 and 9-11 agree
+# within the rounding of the printed three digits (half a unit in the last
+# place: 0.08 %, 0.38 %, 0.50 %, 0.08 %, 0.12 %); the others by what the
+# oracle reaches, rounded up: row 3 +5.40 %, row 4 +3.58 %, row 5 +0.79 %,
+# row 6 +1.18 %, row 7 +0.63 %, row 8 +0.36 %.  The residual of rows 3-4 is
+# not a boundary convention (the maxima sit at the centre of the domain, and
+# ghost x values taken from f instead of computed move them by < 0.3 %).
+LINF_BAND = [0.001, 0.004, 0.055, 0.037, 0.009, 0.0125, 0.007, 0.004, 0.005, 0.001, 0.0015]
+
+
 @pytest.mark.parametrize("i", range(11))
 def test_table1_linf(oracle_mod, i):
     tab = _load("table1_convergence.txt")
     linf = errors(oracle_mod, f1, i, beta=1.0)[0]
     rel = abs(linf / tab[i, 1] - 1)
-    # rows 1, 2 and 9-11 agree to the printed three digits; rows 3-8 within 6 %
-    tol = 0.006 if i in (0, 1, 8, 9, 10) else 0.06
-    assert rel <= tol, (i, linf, tab[i, 1])
+    assert rel <= LINF_BAND[i], (i, linf, tab[i, 1], rel)
 
 
 def test_table1_neighbour_weight_quarter_misses_row2(oracle_mod):
@@ -90,6 +102,15 @@ def test_table1_orders(oracle_mod):
         o_l2 = np.log2(e[k - 1][1] / e[k][1])
         assert abs(o_inf - tab[6 + k, 2]) <= 0.05
         assert abs(o_l2 - tab[6 + k, 4]) <= 0.05
+
+
+def test_table1_l2_fine_rows_constant_factor(oracle_mod):
+    # the RMS over all (2n-1)^2 points is a fixed multiple of the printed L2
+    # error at rows 4-9 (the paper does not state its normalisation)
+    tab = _load("table1_convergence.txt")
+    for i in range(3, 9):
+        ratio = errors(oracle_mod, f1, i, beta=1.0)[1] / tab[i, 3]
+        assert 1.10 <= ratio <= 1.125, (i, ratio)
 
 
 def test_table1_literal_indicator_scale_misses_fine_rows(oracle_mod):
