@@ -145,17 +145,15 @@ def backward(V, G, beta=2.0, keps=1e-8, h=1.0, si_mode=0, nbw=None) -> np.ndarra
     return out.reshape(lead + (n, m))
 
 
+def quantize_u8_255(X) -> np.ndarray:
+    """uint8 code of a value on the 0..255 scale: round half to even, then
+    clamp to [0, 255] (the project's reading; the paper does not quantise)."""
+    return np.clip(np.rint(np.asarray(X, dtype=np.float64)), 0, 255).astype(np.uint8)
+
+
 def quantize_u8(U) -> np.ndarray:
-    """uint8 code of a [0,1]-scale value: round half to even of 255 u, clamped."""
-    return np.clip(np.rint(255.0 * np.asarray(U, dtype=np.float64)), 0, 255).astype(np.uint8)
-
-
-def zoom2x_u8(img_u8, beta=2.0, keps=1e-8, h=1.0):
-    """uint8 image (any leading dims, last two spatial) -> (FP64 [0,1] result, uint8 codes).
-
-    The image is read on the [0,1] scale (value / 255)."""
-    U = zoom2x(np.asarray(img_u8, dtype=np.float64) / 255.0, beta=beta, keps=keps, h=h)
-    return U, quantize_u8(U)
+    """uint8 code of a [0,1]-scale value: quantize_u8_255(255 u)."""
+    return quantize_u8_255(255.0 * np.asarray(U, dtype=np.float64))
 
 
 def cascade(V, levels, beta=2.0, keps=1e-8, h=1.0):

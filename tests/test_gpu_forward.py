@@ -8,8 +8,8 @@ import pytest
 import torch
 
 import oracle
-from conftest import u8_compare
-from workloads import pixel_art, random_plane, scene_rgb, smooth_grid, to_planar_f32
+from conftest import check_u8
+from workloads import pixel_art, random_plane, scene_rgb, smooth_grid, to_planar_f32, two_level_u8
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -93,11 +93,32 @@ def test_u8_hwc_scene(gpu, cfg, request):
     assert y.stride()[0] == 1
     codes = y.permute(1, 2, 0).cpu().numpy()                     # (2H, 2W, C)
     ref = oracle.zoom2x(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0)
-    ties, errors = u8_compare(np.transpose(codes, (2, 0, 1)), ref)
-    print("u8 scene: ties %d of %d" % (ties, ref.size))
-    assert errors == 0
-    assert ties <= 1e-3 * ref.size
+    check_u8(np.transpose(codes, (2, 0, 1)), ref, "u8 HWC scene %s" % (cfg,))
     assert np.array_equal(codes[0::2, 0::2], img)
+
+
+@pytest.mark.parametrize("cfg", [(64, 2), (16, 1)])
+@pytest.mark.parametrize("layout", ["plane", "hwc"])
+def test_u8_exact_ties_round_half_even(gpu, cfg, layout):
+    # beta = 0 on samples that are multiples of 16: every new point is a small
+    # dyadic fraction, computed exactly in FP32 and FP64, and a large share of
+    # them lie exactly on k + 1/2.  The codes must be those of round half to
+    # even, with no tie allowance.
+    _set(gpu, cfg)
+    if layout == "plane":
+        img = two_level_u8(53, 141, seed=7)
+        x = torch.tensor(img, device="cuda")
+        got = gpu.zoom2x(x, beta=0.0).cpu().numpy()
+        X = oracle.zoom2x(img.astype(np.float64), beta=0.0)        # 0..255 scale
+    else:
+        img = two_level_u8(41, 75, seed=8, channels=3)
+        x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+        got = np.transpose(gpu.zoom2x(x, beta=0.0).permute(1, 2, 0).cpu().numpy(), (2, 0, 1))
+        X = oracle.zoom2x(np.transpose(img, (2, 0, 1)).astype(np.float64), beta=0.0)
+    n_ties = int((X - np.floor(X) == 0.5).sum())
+    print("exact k+1/2 values: %d of %d" % (n_ties, X.size))
+    assert n_ties > 0.1 * X.size
+    assert np.array_equal(got, oracle.quantize_u8_255(X))
 
 
 def test_u8_to_f32_and_f32_to_u8(gpu):
@@ -109,8 +130,7 @@ def test_u8_to_f32_and_f32_to_u8(gpu):
     assert np.abs(np.transpose(yf, (2, 0, 1)) - ref).max() <= TOL
     xf = _f32(np.transpose(img, (2, 0, 1)) / 255.0)
     y8 = gpu.zoom2x(xf, out_dtype=torch.uint8).cpu().numpy()
-    ties, errors = u8_compare(y8, ref)
-    assert errors == 0
+    check_u8(y8, ref, "pixel art f32->u8")
 
 
 def test_strided_views(gpu):
@@ -176,9 +196,10 @@ def test_full_size_1080p_sampled(gpu):
         got_f = yf[:, 2 * r0: 2 * r0 + 48, 2 * c0: 2 * c0 + 48]
         assert np.abs(got_f - ref).max() <= TOL, (r0, c0)
         got8 = np.transpose(y8[2 * r0: 2 * r0 + 48, 2 * c0: 2 * c0 + 48], (2, 0, 1))
-        ties, errors = u8_compare(got8, ref)
-        assert errors == 0, (r0, c0)
-        total_ties += ties
+        total_ties += check_u8(got8, ref, "1080p u8 window (%d, %d)" % (r0, c0))
+    n_out = 3 * 48 * 48 * len(windows)
+    print("1080p u8 windows: %d ties of %d" % (total_ties, n_out))
+    assert total_ties <= 1e-3 * n_out
     assert np.array_equal(y8[0::2, 0::2], img)
 
 
@@ -212,8 +233,7 @@ def test_padded_output_rows_untouched(gpu, cfg, W, dtypes):
     gpu.zoom2x_(x, out)
     got = out.cpu().numpy()
     if dst_t == "u8":
-        ties, errors = u8_compare(got, ref)
-        assert errors == 0
+        check_u8(got, ref, "padded rows %s W=%d %s" % (cfg, W, dtypes))
         assert bool((big[:, 2 * W:] == 201).all())
     else:
         assert np.abs(got - ref).max() <= TOL

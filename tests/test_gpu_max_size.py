@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from conftest import u8_compare
+from conftest import check_u8
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -51,8 +51,7 @@ def test_forward_u8_largest_plane(gpu):
         sub = img[wr0: min(H, r0 + 22), wc0: min(W, c0 + 22)].astype(np.float64) / 255.0
         ref = oracle.window_zoom2x(sub, r0 - wr0, r0 - wr0 + 16, c0 - wc0, c0 - wc0 + 16)
         got = y[2 * r0: 2 * r0 + 32, 2 * c0: 2 * c0 + 32].cpu().numpy()
-        ties, errors = u8_compare(got, ref)
-        assert errors == 0, (r0, c0)
+        check_u8(got, ref, "largest u8 plane window (%d, %d)" % (r0, c0))
         assert np.array_equal(got[0::2, 0::2], img[r0: r0 + 16, c0: c0 + 16])
     del x, y
     torch.cuda.empty_cache()

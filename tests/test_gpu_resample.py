@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import u8_compare
+from conftest import check_u8
 from oracle import resample as R
 from workloads import pixel_art, random_plane, scene_rgb
 
@@ -32,8 +32,7 @@ def test_resample_u8_hwc(gpu):
     x = torch.tensor(img, device="cuda").permute(2, 0, 1)
     y = gpu.resample(x, 133, 211)
     ref = R.tensor_resample(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 133, 211)
-    ties, errors = u8_compare(y.cpu().numpy(), ref)
-    assert errors == 0
+    check_u8(y.cpu().numpy(), ref, "resample u8 HWC")
 
 
 @pytest.mark.parametrize("shape,out", [((7, 9), (13, 17)), ((20, 30), (57, 88)), ((33, 40), (20, 25)),
@@ -43,7 +42,8 @@ def test_zoom_to_f32(gpu, shape, out):
     got = gpu.zoom_to(_t(V), *out).cpu().numpy()
     ref = R.zoom_to(V.astype(np.float32).astype(np.float64), *out)
     assert got.shape == ref.shape
-    assert np.abs(got - ref).max() <= 3 * TOL
+    print("zoom_to %s -> %s: max-abs error %.3e" % (shape, out, np.abs(got - ref).max()))
+    assert np.abs(got - ref).max() <= TOL
 
 
 def test_zoom_to_scale3_pixel_art_u8(gpu):
@@ -52,8 +52,7 @@ def test_zoom_to_scale3_pixel_art_u8(gpu):
     x = torch.tensor(img, device="cuda").permute(2, 0, 1)
     y = gpu.zoom_to(x, 96, 120)
     ref = R.zoom_to(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 96, 120)
-    ties, errors = u8_compare(y.cpu().numpy(), ref, tie_band=3 * TOL)
-    assert errors == 0
+    check_u8(y.cpu().numpy(), ref, "zoom_to scale 3 pixel art")
 
 
 def test_quality_protocol_runs(gpu):
@@ -83,8 +82,7 @@ def test_resample_mixed_dtypes(gpu, pair):
         V32 = V.astype(np.float32)
         got = gpu.resample(_t(V32), 71, 30, out_dtype=torch.uint8).cpu().numpy()
         ref = R.tensor_resample(V32.astype(np.float64), 71, 30)
-        ties, errors = u8_compare(got, ref)
-        assert errors == 0
+        check_u8(got, ref, "resample f32->u8")
 
 
 @pytest.mark.parametrize("shape,out", [((41, 77), (150, 301)), ((25, 33), (97, 40))])
@@ -93,7 +91,8 @@ def test_zoom_to_odd_widths_two_levels(gpu, shape, out):
     V = random_plane(*shape, seed=17, kind="steps") * 0.5 + 0.5 * random_plane(*shape, seed=18)
     got = gpu.zoom_to(_t(V), *out).cpu().numpy()
     ref = R.zoom_to(V.astype(np.float32).astype(np.float64), *out)
-    assert np.abs(got - ref).max() <= 3 * TOL
+    print("zoom_to odd widths %s -> %s: max-abs error %.3e" % (shape, out, np.abs(got - ref).max()))
+    assert np.abs(got - ref).max() <= TOL
 
 
 @pytest.mark.parametrize("op", ["resample", "zoom_to"])
@@ -109,7 +108,7 @@ def test_beta0_without_eps(gpu, op):
         got = gpu.zoom_to(_t(V), 100, 151, p).cpu().numpy()
         ref = R.zoom_to(V.astype(np.float64), 100, 151, beta=0.0, keps=0.0)
     assert np.isfinite(got).all()
-    assert np.abs(got - ref).max() <= 3 * TOL
+    assert np.abs(got - ref).max() <= TOL
 
 
 # width ratios 0.58, 1.7, 2.3 (LDS rows of 512 samples per tile), 10.7 (768),
@@ -130,8 +129,7 @@ def test_resample_u8_hwc_many_tiles(gpu):
     x = torch.tensor(img, device="cuda").permute(2, 0, 1)
     y = gpu.resample(x, 300, 913)
     ref = R.tensor_resample(np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0, 300, 913)
-    ties, errors = u8_compare(y.cpu().numpy(), ref)
-    assert errors == 0
+    check_u8(y.cpu().numpy(), ref, "resample u8 HWC many tiles")
 
 
 def test_resample_nodes_are_copies(gpu):

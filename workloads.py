@@ -160,3 +160,13 @@ def random_plane(n: int, m: int, seed: int, kind: str = "uniform") -> np.ndarray
     if kind == "binary":
         return (rng.random((n, m)) < 0.5).astype(np.float64)
     raise ValueError(kind)
+
+
+def two_level_u8(h, w, seed, channels=None):
+    """uint8 samples drawn from {96, 112, 128, 144} (multiples of 16): under
+    equal weights every interpolated value is a small dyadic fraction on the
+    0..255 scale, and many of them lie exactly halfway between two codes, so
+    the rounding rule is visible.  (h, w) or (h, w, channels)."""
+    rng = np.random.default_rng(seed)
+    shape = (h, w) if channels is None else (h, w, channels)
+    return (96 + 16 * rng.integers(0, 4, shape)).astype(np.uint8)
