@@ -70,6 +70,9 @@ def _load():
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Params)] + extra
+        lib.weno_oracle_backward_planes.restype = ctypes.c_int
+        lib.weno_oracle_backward_planes.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.POINTER(_Params), dp, dp]
         _lib = lib
     return _lib
 
@@ -125,7 +128,8 @@ def weights(V, beta=2.0, keps=1e-8, h=1.0, si_mode=0, nbw=None) -> np.ndarray:
 
 
 def backward(V, G, beta=2.0, keps=1e-8, h=1.0, si_mode=0, nbw=None) -> np.ndarray:
-    """Hand adjoint: dL/dV for dL/dU = G, every plane separately."""
+    """Hand adjoint: dL/dV for dL/dU = G, every plane separately (several
+    planes run on separate OpenMP threads)."""
     planes, lead = _planes(V)
     gplanes, glead = _planes(G)
     n, m = planes.shape[-2:]
@@ -134,14 +138,17 @@ def backward(V, G, beta=2.0, keps=1e-8, h=1.0, si_mode=0, nbw=None) -> np.ndarra
     lib = _load()
     p = _params(beta, keps, h, si_mode, nbw)
     out = np.empty(planes.shape, dtype=np.float64)
-    for c in range(planes.shape[0]):
-        src = np.ascontiguousarray(planes[c])
-        g = np.ascontiguousarray(gplanes[c])
-        dst = np.empty((n, m), dtype=np.float64)
-        rc = lib.weno_oracle_backward(_dptr(src), n, m, ctypes.byref(p), _dptr(g), _dptr(dst))
+    if planes.shape[0] > 1:   # one plane per OpenMP thread
+        g = np.ascontiguousarray(gplanes)
+        rc = lib.weno_oracle_backward_planes(_dptr(planes), planes.shape[0], n, m, ctypes.byref(p), _dptr(g),
+                                             _dptr(out))
         if rc != 0:
-            raise ValueError("weno_oracle_backward failed with status %d" % rc)
-        out[c] = dst
+            raise ValueError("weno_oracle_backward_planes failed with status %d" % rc)
+        return out.reshape(lead + (n, m))
+    g = np.ascontiguousarray(gplanes[0])
+    rc = lib.weno_oracle_backward(_dptr(planes[0]), n, m, ctypes.byref(p), _dptr(g), _dptr(out[0]))
+    if rc != 0:
+        raise ValueError("weno_oracle_backward failed with status %d" % rc)
     return out.reshape(lead + (n, m))
 
 

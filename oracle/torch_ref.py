@@ -10,6 +10,15 @@ positions) rather than on the fine grid of the C oracle:
   B(I, J)  phase-2 point at (I, J + 1/2), horizontal stencils on originals,
            vertical stencils on X.
 
+`rounding` (optional): a function applied to every intermediate the
+formulas produce (candidates, stencil differences, indicators, eps + D,
+weights, their sum, blends).  Passing a random relative perturbation of the
+size of a unit roundoff makes this Monte Carlo arithmetic (D. S. Parker,
+"Monte Carlo arithmetic: exploiting randomness in floating-point
+arithmetic", 1997): the spread of the results, and of their autograd
+gradients, over a few draws estimates how far rounding at that precision can
+move any evaluation of these formulas.
+
 Candidate of a stencil (a, b, c) at nodes -1, 1, 3 evaluated at 0:
 (3a + 6b - c)/8.  Indicator with the interval-length scale:
 (b - a)^2 + 13/12 (a - 2b + c)^2 (the integral of eq. 2Dsmoothness worked out
@@ -23,22 +32,25 @@ import torch
 M = 6  # coarse margin of the padded input
 
 
-def _cand(a, b, c):
-    return (3.0 * a + 6.0 * b - c) / 8.0
+def _exact(x):
+    return x
 
 
-def _si(a, b, c):
-    return (b - a) ** 2 + (13.0 / 12.0) * (a - 2.0 * b + c) ** 2
-
-
-def _blend(ps, Ds, eps, beta):
-    alphas = [0.5 / (eps + D) ** beta for D in Ds]
-    tot = alphas[0] + alphas[1] + alphas[2] + alphas[3]
-    return sum(a * p for a, p in zip(alphas, ps)) / tot
-
-
-def zoom2x(V: torch.Tensor, beta=2.0, keps=1e-8, h=1.0, nbw=None) -> torch.Tensor:
+def zoom2x(V: torch.Tensor, beta=2.0, keps=1e-8, h=1.0, nbw=None, rounding=None) -> torch.Tensor:
     """V: (..., n, m) float64 -> (..., 2n, 2m)."""
+    r = rounding or _exact
+
+    def _cand(a, b, c):
+        return r((3.0 * a + 6.0 * b - c) / 8.0)
+
+    def _si(a, b, c):
+        return r(r(b - a) ** 2 + (13.0 / 12.0) * r(a - 2.0 * b + c) ** 2)
+
+    def _blend(ps, Ds, eps, beta):
+        alphas = [r(0.5 / r(eps + D) ** beta) for D in Ds]
+        tot = r(alphas[0] + alphas[1] + alphas[2] + alphas[3])
+        return r(sum(a * p for a, p in zip(alphas, ps)) / tot)
+
     n, m = V.shape[-2:]
     eps = keps * h * h
     w = h * h / 8.0 if nbw is None else nbw

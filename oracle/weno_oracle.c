@@ -466,3 +466,23 @@ int weno_oracle_backward(const double* V, int n, int m, const weno_oracle_params
     st_free(&s);
     return WO_OK;
 }
+
+/* The hand adjoint of `planes` independent planes, one plane per OpenMP
+ * thread (V: planes x n x m, G: planes x 2n x 2m, gV: planes x n x m, all
+ * row-major).  Each plane is weno_oracle_backward, unchanged. */
+int weno_oracle_backward_planes(const double* V, int planes, int n, int m, const weno_oracle_params* p,
+                                const double* G, double* gV)
+{
+    if (planes < 1) return WO_EINVAL;
+    int rc = WO_OK;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < planes; ++c) {
+        const size_t in = (size_t)n * (size_t)m;
+        int r = weno_oracle_backward(V + (size_t)c * in, n, m, p, G + (size_t)c * 4 * in, gV + (size_t)c * in);
+        if (r) {
+            #pragma omp critical
+            rc = r;
+        }
+    }
+    return rc;
+}

@@ -31,12 +31,15 @@
 //   output      dL/dV row s-4 is complete: fold clamped rows/columns onto the
 //               edge pixels and store.
 // Valid lanes shrink with every neighbour access: the dL/dV of lanes 9..54 is
-// exact.  The first strip of a row starts at lane 13 so that the four padded
-// columns left of the image (folded onto column 0) fall in lanes 9..12 and
-// owns 42 columns; the last starts at lane 9 and owns at most 42, which leaves
-// lanes up to 54 for the four padded columns right of the image; the strips
-// between own all 46 exact lanes.  A strip that is both first and last holds
-// at most 38 columns, so images 39..42 wide are split into two strips of 21.
+// exact.  A quad reads inputs I-4 .. I+5 and J-4 .. J+5, so clamped reads
+// reach four padded columns left of the image and five right of it (rows
+// likewise: four above, five below), all folded onto the edge pixels.  The
+// first strip of a row starts at lane 13 so that the four padded columns
+// left of the image fall in lanes 9..12 and owns 42 columns; the last starts
+// at lane 9 and owns at most 41, which leaves lanes up to 54 for the five
+// padded columns right of the image; the strips between own all 46 exact
+// lanes.  A strip that is both first and last holds at most 37 columns, so
+// images 38..42 wide are split into two strips of 21 and the rest.
 #pragma once
 
 #include <stdint.h>
@@ -51,17 +54,18 @@ constexpr int kBwdLane0First = 13; // lane of the first owned column, first stri
 constexpr int kBwdLane0 = 9;       // lane of the first owned column, other strips
 constexpr int kBwdOwnFirst = 42;   // columns of the first strip of a row (lanes 13..54)
 constexpr int kBwdOwnMid = 46;     // columns of a strip between the first and the last (lanes 9..54)
-constexpr int kBwdOwnLast = 42;    // at most, in the last strip (its padding takes lanes up to 54)
+constexpr int kBwdOwnLast = 41;    // at most, in the last strip (its five padded columns take lanes up to 54)
+constexpr int kBwdOwnSingle = 37;  // at most, in a strip that is both first and last (lanes 13..49)
 
 // Strip layout along a row of W columns (host and device).  The exact lanes
 // of a strip are 9..54.  The first strip owns columns from lane 13 (lanes
 // 9..12 carry the four padded columns left of the image), the last owns at
-// most 42 so that the four padded columns right of the image fall in lanes up
+// most 41 so that the five padded columns right of the image fall in lanes up
 // to 54, and strips in between own all 46.  A strip that is both first and
-// last holds at most 38 columns: widths 39..42 are two strips of 21.
+// last holds at most 37 columns: widths 38..42 are two strips, 21 and W - 21.
 __host__ __device__ inline int bwd_strip_count(int W)
 {
-    if (W <= 38) return 1;
+    if (W <= kBwdOwnSingle) return 1;
     if (W <= 42) return 2;
     const int R = W - kBwdOwnFirst;   // columns after the first strip
     if (R <= kBwdOwnLast) return 2;
@@ -71,7 +75,7 @@ __host__ __device__ inline int bwd_strip_count(int W)
 // first column c0 and width of strip sx of a row of W columns
 __host__ __device__ inline void bwd_strip_span(int W, int sx, int& c0, int& width)
 {
-    if (W <= 38) {
+    if (W <= kBwdOwnSingle) {
         c0 = 0;
         width = W;
         return;
@@ -106,7 +110,8 @@ __host__ __device__ inline void bwd_strip_span(int W, int sx, int& c0, int& widt
 // from a+9, their adjoint from a+10, complete dL/dx rows from a+11 and the
 // x-point adjoint from a+15; that last one feeds dL/dV rows r-1 .. r+2, so
 // the first exact dL/dV row is a+14.  The top strip also folds the padded
-// rows -4..-1 onto row 0, so it starts 4 rows earlier.
+// rows -4..-1 onto row 0, so it starts 4 rows earlier; the bottom strip walks
+// on until dL/dV row H+4, the last padded row a quad of row H-1 reads.
 constexpr int kBwdWarm = 14;
 constexpr int kBwdWarmTop = 18;
 // The first 9 iterations of a walk from row a run the forward pipeline only.
@@ -254,7 +259,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     float accV_m4 = 0, accV_m3 = 0, accV_m2 = 0, accV_m1 = 0, accV_0 = 0;  // dL/dV rows s-4 .. s
     float fold_top = 0, held = 0;
 
-    const int s_end = bottom ? H + 7 : R1 + 3;
+    const int s_end = bottom ? H + 8 : R1 + 3;   // dL/dV row s - 4 completes at step s
     int s = R0 - (top ? kBwdWarmTop : kBwdWarm);
     // loads run ahead of their use: V two rows, dL/dU one step
     float Q0 = ldV(s + 5), Q1 = ldV(s + 6);
@@ -480,7 +485,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         if constexpr (P1) {
             const int r = s - 4;
             float val = accV_m4 + gVu;
-            // clamped columns: padded columns -4..-1 fold onto column 0, W..W+3 onto W-1
+            // clamped columns: padded columns -4..-1 fold onto column 0, W..W+4 onto W-1
             if (first_strip) {
                 float p = J < 0 ? val : 0.0f, acc = -0.0f;
 #pragma unroll
@@ -490,10 +495,10 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             if (last_strip) {
                 float q = J >= W ? val : 0.0f, acc = -0.0f;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) { q = nbR(q); acc += q; }
+                for (int k = 0; k < 5; ++k) { q = nbR(q); acc += q; }
                 if (J == W - 1) val += acc;
             }
-            // clamped rows: rows -4..-1 fold onto row 0, rows H..H+3 onto row H-1
+            // clamped rows: rows -4..-1 fold onto row 0, rows H..H+4 onto row H-1
             if (top && r < 0) {
                 if (r >= -4) fold_top += val;   // padded rows -4..-1; earlier rows are pipeline fill
             } else if (bottom && r >= H - 1) {

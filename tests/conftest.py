@@ -76,3 +76,22 @@ def check_u8(gpu_codes, oracle_u, label, tie_band=1e-5, max_tie_frac=1e-4):
     return ties
 
 
+def check_adjoint(got, V32, G, label, mca_slice=None, **kw):
+    """Adjoint parity against the FP64 oracle: max |got - ref| <= bar x max |ref|
+    with bar = max(1e-5, 4 x the FP32 Monte Carlo arithmetic spread of the
+    gradient at this input; oracle.mca).  The spread is taken on
+    V32[mca_slice] (a representative part of a large batch) when given."""
+    import oracle
+    from oracle import mca
+
+    V64 = np.asarray(V32, dtype=np.float32).astype(np.float64)
+    G64 = np.asarray(G, dtype=np.float32).astype(np.float64)
+    okw = {k: v for k, v in kw.items() if k in ("beta", "keps", "h", "nbw")}
+    ref = oracle.backward(V64, G64, **okw)
+    sl = slice(None) if mca_slice is None else mca_slice
+    bar, spread = mca.adjoint_bar(V64[sl], G64[sl], ref[sl], **okw)
+    scale = float(np.abs(ref).max())
+    err = float(np.abs(np.asarray(got, dtype=np.float64) - ref).max()) / max(scale, 1e-300)
+    print("%s: adjoint rel err %.2e, FP32 Monte Carlo spread %.2e, bar %.2e" % (label, err, spread, bar))
+    assert err <= bar, (label, err, bar)
+    return err

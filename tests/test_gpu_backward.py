@@ -2,38 +2,34 @@
 against the oracle's hand adjoint (itself pinned to torch FP64 autograd and
 central finite differences in the CPU suite).
 
-Tolerance: FP32 seeds carry (p_k - u)/t_k, a difference of O(1) values
-divided by an O(h^2) quantity in smooth regions, so relative rounding of the
-largest gradient entries reaches ~2e-5; the bar is max-abs error
-<= 1e-4 * max(1, max|ref|)."""
+Bar (conftest.check_adjoint): max |got - ref| <= bar * max |ref| with bar =
+max(1e-5, 4 x the spread that Monte Carlo arithmetic at FP32 unit roundoff
+gives the oracle's own gradient at that input, oracle.mca).  Well-conditioned
+inputs keep the 1e-5 bar (the kernel reaches ~1e-6); next to flat regions the
+gradient divides by t = eps + D close to eps and FP32 rounding of the formulas
+alone moves it by up to ~1e-4, which the bar follows.  The whole 16x3x512^2
+batch is checked in test_gpu_full_size.py."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from conftest import check_adjoint
 from workloads import random_plane, scene_rgb, to_planar_f32
 
 pytestmark = pytest.mark.gpu
-RTOL = 1e-4
 
 
 def _t(a):
     return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
 
 
-def _ref(V, G, **kw):
-    return oracle.backward(V.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64), **kw)
-
-
-def _close(got, ref):
-    return np.abs(got - ref).max() <= RTOL * max(1.0, np.abs(ref).max())
-
-
 SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (7, 77), (40, 39), (65, 120), (130, 37), (64, 38), (3, 200),
-          # strip layout boundaries: one strip up to 38 columns, two of 21 for 39..42, first + last (42 + up
-          # to 42) up to 84, then middle strips of 46 (85: 42 | 42 | 1, 130: 42 | 46 | 42, 131: 42 | 46 |
-          # 42 | 1, 177/178: three or four strips)
-          (6, 42), (5, 43), (11, 84), (9, 85), (12, 126), (7, 127), (6, 130), (5, 131), (4, 177), (3, 178)]
+          # strip layout boundaries: one strip up to 37 columns, two (21 | W - 21) for 38..42, first + last
+          # (42 + up to 41) up to 83, then middle strips of 46 (84: 42 | 41 | 1, 129: 42 | 46 | 41,
+          # 130: 42 | 46 | 41 | 1, 175/176: four or five strips)
+          (6, 37), (5, 38), (6, 42), (5, 43), (11, 83), (11, 84), (9, 85), (12, 129), (6, 130), (5, 131),
+          (4, 175), (3, 176), (4, 177)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -42,7 +38,7 @@ def test_backward_matches_oracle(gpu, shape):
     V = random_plane(*shape, seed=5, kind="steps") * 0.7 + 0.3 * rng.random(shape)
     G = rng.standard_normal((2 * shape[0], 2 * shape[1]))
     got = gpu.zoom2x_backward(_t(V), _t(G)).cpu().numpy()
-    assert _close(got, _ref(V, G))
+    check_adjoint(got, V, G, "shape %s" % (shape,))
 
 
 @pytest.mark.parametrize("beta", [0.0, 0.5, 1.0, 2.0, 3.0])
@@ -53,7 +49,7 @@ def test_backward_beta(gpu, beta, kind):
     G = rng.standard_normal((66, 142))
     p = gpu.Params(beta=beta)
     got = gpu.zoom2x_backward(_t(V), _t(G), p).cpu().numpy()
-    assert _close(got, _ref(V, G, beta=beta))
+    check_adjoint(got, V, G, "beta %.1f %s" % (beta, kind), beta=beta)
 
 
 @pytest.mark.parametrize("kind", ["binary", "steps"])
@@ -65,7 +61,7 @@ def test_backward_beta0_without_eps(gpu, kind):
     G = rng.standard_normal((58, 126))
     got = gpu.zoom2x_backward(_t(V), _t(G), gpu.Params(beta=0.0, k_eps=0.0)).cpu().numpy()
     assert np.isfinite(got).all()
-    assert _close(got, _ref(V, G, beta=0.0, keps=0.0))
+    check_adjoint(got, V, G, "beta 0 without eps %s" % kind, beta=0.0, keps=0.0)
 
 
 @pytest.mark.parametrize("nbw,h", [(0.25, 1.0), (0.0, 1.0), (-1.0, 0.25)])
@@ -74,7 +70,7 @@ def test_backward_parameters(gpu, nbw, h):
     V = random_plane(20, 50, seed=2, kind="steps") * 0.5 + 0.5 * rng.random((20, 50))
     G = rng.standard_normal((40, 100))
     got = gpu.zoom2x_backward(_t(V), _t(G), gpu.Params(nbw=nbw, h=h)).cpu().numpy()
-    assert _close(got, _ref(V, G, nbw=None if nbw < 0 else nbw, h=h))
+    check_adjoint(got, V, G, "nbw %g h %g" % (nbw, h), nbw=None if nbw < 0 else nbw, h=h)
 
 
 def test_backward_batch_and_strides(gpu):
@@ -82,11 +78,11 @@ def test_backward_batch_and_strides(gpu):
     V = rng.random((2, 3, 21, 45)).astype(np.float32)
     G = rng.standard_normal((2, 3, 42, 90)).astype(np.float32)
     got = gpu.zoom2x_backward(_t(V), _t(G)).cpu().numpy()
-    assert _close(got, _ref(V, G))
+    check_adjoint(got, V, G, "batch 2x3")
     # channels-interleaved input view
     x_hwc = _t(np.transpose(V[0], (1, 2, 0))).permute(2, 0, 1)
     got2 = gpu.zoom2x_backward(x_hwc, _t(G[0])).cpu().numpy()
-    assert _close(got2, _ref(V[0], G[0]))
+    check_adjoint(got2, V[0], G[0], "HWC view")
 
 
 def test_backward_into_callers_output(gpu):
@@ -137,7 +133,7 @@ def test_autograd_function(gpu):
     y = gpu.WenoZoom2x.apply(x)
     G = rng.standard_normal(y.shape)
     (y * _t(G)).sum().backward()
-    assert _close(x.grad.cpu().numpy(), _ref(V, G))
+    check_adjoint(x.grad.cpu().numpy(), V, G, "autograd function")
 
 
 def test_finite_differences_fp64_16x16(gpu):
@@ -151,24 +147,6 @@ def test_finite_differences_fp64_16x16(gpu):
     fd = ((oracle.zoom2x(V + eps * D) - oracle.zoom2x(V - eps * D)) * G).sum() / (2 * eps)
     got = gpu.zoom2x_backward(_t(V), _t(G)).cpu().numpy().astype(np.float64)
     assert abs((got * D).sum() - fd) <= 1e-4 * max(1.0, abs(fd))
-
-
-def test_full_size_sampled_windows(gpu):
-    # 16 x 3 x 512 x 512 float32 batch; gradient windows checked against the
-    # oracle adjoint computed on input windows 12 pixels larger on each side
-    imgs = np.stack([to_planar_f32(scene_rgb(512, 512, seed=100 + i, n_polygons=20)) for i in range(16)])
-    rng = np.random.default_rng(8)
-    G = rng.standard_normal((16, 3, 1024, 1024)).astype(np.float32)
-    got = gpu.zoom2x_backward(_t(imgs), _t(G)).cpu().numpy()
-    M = 12
-    for (b, c, r0, c0) in [(0, 0, 0, 0), (3, 1, 500, 490), (15, 2, 200, 300), (7, 0, 0, 480), (9, 2, 490, 0)]:
-        r1, c1 = r0 + 12, c0 + 12
-        wr0, wr1 = max(0, r0 - M), min(512, r1 + M)
-        wc0, wc1 = max(0, c0 - M), min(512, c1 + M)
-        Vw = imgs[b, c, wr0:wr1, wc0:wc1]
-        Gw = G[b, c, 2 * wr0:2 * wr1, 2 * wc0:2 * wc1]
-        ref = _ref(Vw, Gw)[r0 - wr0:r1 - wr0, c0 - wc0:c1 - wc0]
-        assert _close(got[b, c, r0:r1, c0:c1], ref), (b, c, r0, c0)
 
 
 def test_inverse_problem_recovers_input(gpu):

@@ -4,13 +4,13 @@ planar or channel-interleaved layouts, float32 or uint8 at either end, beta
 in {1, 1.5, 2}, automatic or forced launch shapes; the adjoint on float32;
 the resampler up and down.  The bars are those of the targeted tests:
 float32 within 1e-5 of max(1, |ref|), uint8 codes equal up to counted
-rounding ties, the adjoint within 1e-4 of max(1, |ref|)."""
+rounding ties, the adjoint within the bar of conftest.check_adjoint."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from conftest import check_u8
+from conftest import check_adjoint, check_u8
 from oracle import resample as R
 
 pytestmark = pytest.mark.gpu
@@ -82,8 +82,7 @@ def test_random_backward(gpu, seed):
                                   gpu.Params(beta=beta)).cpu().numpy()
     finally:
         gpu.set_backward_launch_config(0)
-    ref = oracle.backward(V.astype(np.float64), G.astype(np.float64), beta=beta)
-    assert np.abs(got - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max()), (seed, h, w, n, c, beta, rows)
+    check_adjoint(got, V, G, str((seed, h, w, n, c, beta, rows)), beta=beta)
 
 
 @pytest.mark.parametrize("seed", range(200, 216))

@@ -11,6 +11,7 @@ import torch
 
 import oracle
 from oracle import resample as R
+from conftest import check_adjoint
 from workloads import random_plane
 
 pytestmark = pytest.mark.gpu
@@ -51,10 +52,9 @@ def test_resample_across_magnitudes(gpu, scale, out):
 def test_adjoint_across_magnitudes(gpu, scale):
     """The map is homogeneous of degree one where eps is negligible, so the
     gradient keeps its magnitude across sample scales; parity with the FP64
-    hand adjoint within 1e-4 of max(1, |ref|)."""
+    hand adjoint within the bar of conftest.check_adjoint."""
     V = _plane(29, 90, seed=17, scale=scale)
     G = np.random.default_rng(17).standard_normal((58, 180)).astype(np.float32)
     got = gpu.zoom2x_backward(_f32(V), _f32(G)).cpu().numpy()
-    ref = oracle.backward(V.astype(np.float64), G.astype(np.float64))
     assert np.isfinite(got).all()
-    assert np.abs(got - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max()), scale
+    check_adjoint(got, V, G, "adjoint at scale %g" % scale)

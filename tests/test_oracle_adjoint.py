@@ -59,3 +59,47 @@ def test_adjoint_beta0_is_the_transpose(oracle_mod, kind):
     assert abs(lhs - (D * gv).sum()) <= 1e-12 * max(1.0, abs(lhs))
     # and eps plays no part in it
     assert np.array_equal(gv, oracle_mod.backward(V, G, beta=0.0, keps=1e-8))
+
+
+def test_backward_of_many_planes_is_per_plane(oracle_mod):
+    # the multi-plane entry runs the planes on separate threads: same numbers
+    rng = np.random.default_rng(2)
+    V = rng.random((5, 17, 23))
+    G = rng.standard_normal((5, 34, 46))
+    many = oracle_mod.backward(V, G)
+    for c in range(5):
+        assert np.array_equal(many[c], oracle_mod.backward(V[c], G[c]))
+
+
+def test_mca_spread_measures_fp32_conditioning(oracle_mod):
+    """Monte Carlo arithmetic at FP32 unit roundoff (oracle.mca): small where
+    the gradient is well conditioned, large next to flat regions where the
+    adjoint divides by t = eps + D close to eps (eq. alpha)."""
+    from oracle import mca
+
+    rng = np.random.default_rng(1)
+    G = rng.standard_normal((66, 142))
+    smooth = random_plane(33, 71, seed=9, kind="uniform").astype(np.float32).astype(np.float64)
+    steps = random_plane(33, 71, seed=9, kind="steps").astype(np.float32).astype(np.float64)
+    s_smooth = mca.adjoint_spread(smooth, G, oracle_mod.backward(smooth, G))
+    s_steps = mca.adjoint_spread(steps, G, oracle_mod.backward(steps, G, beta=3.0), beta=3.0)
+    assert 1e-8 < s_smooth < 1e-6
+    assert s_steps > 1e-5
+    bar, spread = mca.adjoint_bar(smooth, G, oracle_mod.backward(smooth, G))
+    assert bar == mca.ADJ_FLOOR and spread == s_smooth
+
+
+def test_mca_rounding_hook_is_the_restatement(oracle_mod):
+    # no perturbation: the hooked restatement is the plain one, bit for bit
+    V = torch.tensor(random_plane(9, 13, seed=2, kind="steps"))
+    a = torch_ref.zoom2x(V)
+    b = torch_ref.zoom2x(V, rounding=lambda t: t)
+    assert torch.equal(a, b)
+    # one unit roundoff per intermediate moves the forward by a few units
+    gen = torch.Generator().manual_seed(0)
+    from oracle import mca
+
+    c = torch_ref.zoom2x(V, rounding=lambda t: t * (1 + mca.U32 * (2 * torch.rand(t.shape, generator=gen,
+                                                                                   dtype=torch.float64) - 1)))
+    rel = float((c - a).abs().max() / a.abs().max())
+    assert 1e-9 < rel < 1e-6
