@@ -35,10 +35,11 @@
  *     error, text from weno_status_string) and never aborts.  Argument
  *     errors are detected on the host before anything is enqueued.
  *   - Non-finite inputs propagate; they are not checked.
- *   - Float samples are supported up to 1e8 in magnitude: the kernels square
- *     sums of squared differences in FP32 (the doubling's weights 1/t^2, the
- *     resampler's E0^2 / (E0^2 + k E1^2)), which leave the FP32 range for
- *     samples of about 1e9 and beyond.
+ *   - Float samples are supported up to 1e8 in magnitude at beta <= 2: the
+ *     kernels square sums of squared differences in FP32 (the doubling's
+ *     weights 1/t^2, the resampler's E0^2 / (E0^2 + k E1^2)), which leave the
+ *     FP32 range for samples of about 1e9 and beyond; larger beta narrows
+ *     the range (t^-beta underflows where every direction is rough).
  *   - Thread safety: calls may come from several host threads; the only
  *     process-global state is the launch configuration set by
  *     weno_set_launch_config (read at each call).
@@ -84,8 +85,12 @@ typedef struct {
 } weno_tensor_t;
 
 typedef struct {
-    float beta;   /* exponent of the nonlinear weights, eq. (alpha); >= 0.  The
-                     paper's images use 2, its convergence table 1.            */
+    float beta;   /* exponent of the nonlinear weights, eq. (alpha); in
+                     [0, 64].  The paper's images use 2, its convergence
+                     table 1.  With beta > 0, eps = k_eps h^2 must be > 0 and
+                     keep the sum of four weights finite in FP32:
+                     beta * log2((12/13) eps) >= -124 (WENO_EINVAL otherwise;
+                     e.g. beta <= 4 at eps = 1e-8).                           */
     float k_eps;  /* eps_h = k_eps * h^2 (Section 2, eq. IzrazOmega); >= 0,
                      the paper's usual value 1e-8                              */
     float h;      /* input grid spacing (> 0); 1 for images                    */

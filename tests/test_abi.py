@@ -96,6 +96,25 @@ def test_parameter_errors(p):
     assert call_zoom(_t(), _t(ptr=0x100000, h=8, w=10), p) == _lib.WENO_EINVAL
 
 
+def _plan_status(p):
+    # the batched plan checks the parameters first and the workspace size
+    # after them: ENOSPC (with a workspace of 0 bytes) means they passed
+    L = _lib.lib()
+    src = (WenoTensor * 1)(_t())
+    dst = (WenoTensor * 1)(_t(ptr=0x100000, h=8, w=10))
+    return L.weno_zoom2x_batched_plan(src, dst, 1, ctypes.byref(p), 0x300000, 0, None, ctypes.byref(WenoBatchPlan()))
+
+
+def test_weight_sum_limit():
+    # four weights t^-beta at the smallest t = (12/13) eps must sum below FP32's
+    # range: 4 ((12/13) eps)^-beta < 2^126
+    assert _plan_status(_p(beta=64.0, keps=0.273)) == _lib.WENO_EINVAL    # each weight ~2^127
+    assert _plan_status(_p(beta=64.0, keps=0.35)) == _lib.WENO_ENOSPC     # ~2^104: accepted
+    assert _plan_status(_p(beta=2.0, keps=1e-8)) == _lib.WENO_ENOSPC
+    assert _plan_status(_p(beta=4.0, keps=1e-8)) == _lib.WENO_ENOSPC     # 2^110
+    assert _plan_status(_p(beta=5.0, keps=1e-8)) == _lib.WENO_EINVAL     # 2^137
+
+
 def test_beta_zero_allows_zero_eps_validation():
     # beta = 0 gives equal weights, eps never enters; validation alone (a
     # shape error is planted so nothing is launched)
