@@ -156,6 +156,26 @@ int weno_zoom2x_batched(const weno_tensor_t* srcs, const weno_tensor_t* dsts, in
                         const weno_params_t* p, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): weno_zoom2x_batched without a caller
+ * workspace.  The image table and the queue head live in a fixed device
+ * array inside the library, one per GPU, kept until the process ends
+ * (about 700 KB).  The call allocates nothing; like weno_zoom2x_batched it
+ * copies the table to the device and waits for the stream once before the
+ * launch (so it cannot be captured into a graph; use the plan/run pair with a
+ * caller workspace for that).
+ *   count: 1 .. WENO_NOALLOC_MAX_IMAGES, else WENO_EINVAL (< 1) or
+ *          WENO_ENOSPC (more images than the fixed array holds).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (from several host threads or on several streams without ordering) race
+ * and must be serialised by the caller.  Outputs are bit-identical to
+ * weno_zoom2x_batched with the same launch configuration.
+ */
+#define WENO_NOALLOC_MAX_IMAGES 4096
+int weno_zoom2x_batched_noalloc(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count,
+                                const weno_params_t* p, void* hip_stream);
+
+/*
  * `levels` successive doublings (eq. zoomfactor), FP32 intermediates in the
  * caller's workspace, the grid spacing halved at each level (h, h/2, ...).
  *   src: (n, c, h, w); dst: (n, c, 2^levels h, 2^levels w); 1 <= levels <= 8.

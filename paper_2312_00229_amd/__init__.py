@@ -196,6 +196,25 @@ def zoom2x_batched(xs, params: Params | None = None, out_dtype=None):
     return BatchedZoom(xs, outs, params).run()
 
 
+def zoom2x_batched_noalloc(xs, outs=None, params: Params | None = None, out_dtype=None):
+    """zoom2x_batched without a workspace: the library keeps the image table in
+    its own fixed device array (at most WENO_NOALLOC_MAX_IMAGES images; calls
+    that overlap on one GPU race).  `outs` (optional): the caller's outputs."""
+    if not xs:
+        raise ValueError("need at least one input")
+    if outs is None:
+        outs = [_empty_like_layout(x, 2, out_dtype or x.dtype) for x in xs]
+    if len(outs) != len(xs):
+        raise ValueError("need as many outputs as inputs")
+    count = len(xs)
+    srcs = (WenoTensor * count)(*[_desc(t) for t in xs])
+    dsts = (WenoTensor * count)(*[_desc(t) for t in outs])
+    p = (params or Params()).c()
+    _lib.check(_lib.lib().weno_zoom2x_batched_noalloc(srcs, dsts, count, ctypes.byref(p), _stream(xs[0].device)),
+               "weno_zoom2x_batched_noalloc")
+    return outs
+
+
 def zoom2x_cascade(x: torch.Tensor, levels: int, params: Params | None = None, out_dtype=None,
                    workspace: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """`levels` successive doublings (eq. zoomfactor) with FP32 intermediates,

@@ -17,6 +17,7 @@ WENO_U8 = 0
 WENO_F32 = 1
 WENO_BOUNDARY_CLAMP = 0
 WENO_BOUNDARY_EXTERNAL = 1
+WENO_NOALLOC_MAX_IMAGES = 4096
 
 
 class WenoTensor(ctypes.Structure):
@@ -70,6 +71,7 @@ _SIGS = {
                                       ctypes.POINTER(WenoBatchPlan)]),
     "weno_zoom2x_batched_run": (_I, [ctypes.POINTER(WenoBatchPlan), _V]),
     "weno_zoom2x_batched": (_I, [_T, _T, ctypes.c_int32, _P, _V, ctypes.c_size_t, _V]),
+    "weno_zoom2x_batched_noalloc": (_I, [_T, _T, ctypes.c_int32, _P, _V]),
     "weno_zoom2x_cascade_workspace": (ctypes.c_size_t, [_T, ctypes.c_int32]),
     "weno_zoom2x_cascade": (_I, [_T, _T, ctypes.c_int32, _P, _V, ctypes.c_size_t, _V]),
     "weno_zoom2x_backward": (_I, [_T, _T, _T, _P, _V]),

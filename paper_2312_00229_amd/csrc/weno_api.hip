@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -151,7 +152,7 @@ extern "C" const char* weno_status_string(int status)
     case WENO_EINVAL: return "invalid argument (null pointer, size, shape or parameter)";
     case WENO_EDTYPE: return "unsupported dtype combination";
     case WENO_EOVERLAP: return "output overlaps an input";
-    case WENO_ENOSPC: return "workspace too small";
+    case WENO_ENOSPC: return "workspace too small (weno_zoom2x_batched_noalloc: more images than its fixed scratch holds)";
     case WENO_EHIP:
         if (g_status_text.empty()) return "HIP runtime error";
         return g_status_text.c_str();
@@ -505,15 +506,12 @@ extern "C" size_t weno_zoom2x_batched_workspace(int32_t count)
     return batch_table_bytes(count);
 }
 
-extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count,
-                                        const weno_params_t* p, void* d_workspace, size_t ws_bytes,
-                                        void* hip_stream, weno_batch_plan_t* plan)
+// argument rules of a batched call (host only, nothing is touched on the device)
+static int batched_check(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count, const weno_params_t* p)
 {
-    if (!srcs || !dsts || !plan || count < 1 || !d_workspace) return WENO_EINVAL;
+    if (!srcs || !dsts || count < 1) return WENO_EINVAL;
     int rc = wz_check_params(p);
     if (rc) return rc;
-    if ((uintptr_t)d_workspace % 256 != 0) return WENO_EINVAL;
-    if (ws_bytes < batch_table_bytes(count)) return WENO_ENOSPC;
     for (int i = 0; i < count; ++i) {
         rc = wz_check_pair(&srcs[i], &dsts[i], 2);
         if (rc) return rc;
@@ -540,6 +538,20 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
             if (v.out) end_out = std::max(end_out, v.hi); else end_in = std::max(end_in, v.hi);
         }
     }
+    return WENO_OK;
+}
+
+extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count,
+                                        const weno_params_t* p, void* d_workspace, size_t ws_bytes,
+                                        void* hip_stream, weno_batch_plan_t* plan)
+{
+    if (!srcs || !dsts || !plan || count < 1 || !d_workspace) return WENO_EINVAL;
+    int rc = wz_check_params(p);
+    if (rc) return rc;
+    if ((uintptr_t)d_workspace % 256 != 0) return WENO_EINVAL;
+    if (ws_bytes < batch_table_bytes(count)) return WENO_ENOSPC;
+    rc = batched_check(srcs, dsts, count, p);
+    if (rc) return rc;
     int rows = g_rows_per_strip.load(), cols = g_cols_per_lane.load();
     if (rows == 0 || cols == 0) {  // the queue balances the load: moderate strips, two columns per lane
         rows = 32;
@@ -630,6 +642,57 @@ extern "C" int weno_zoom2x_batched(const weno_tensor_t* srcs, const weno_tensor_
 {
     weno_batch_plan_t plan;
     int rc = weno_zoom2x_batched_plan(srcs, dsts, count, p, d_workspace, ws_bytes, hip_stream, &plan);
+    if (rc) return rc;
+    return weno_zoom2x_batched_run(&plan, hip_stream);
+}
+
+// --------------------------------------------------------------------------
+// batched, without a caller workspace
+// --------------------------------------------------------------------------
+// The image table and queue head of weno_zoom2x_batched_noalloc live in this
+// file-scope device array (one copy per GPU, alive until the process ends).
+// In host code its name is only a stand-in for the symbol: the device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is ever handed to a copy or a kernel.
+constexpr size_t kNoAllocScratchBytes = batch_table_bytes(WENO_NOALLOC_MAX_IMAGES);
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];  // device address of `scratch` per device, set on first use
+
+static int noalloc_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return wz_hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return WENO_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the current device's copy
+        if (e != hipSuccess) return wz_hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || (uintptr_t)ptr % 256 != 0) return wz_hip_error(hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return WENO_OK;
+}
+
+extern "C" int weno_zoom2x_batched_noalloc(const weno_tensor_t* srcs, const weno_tensor_t* dsts, int32_t count,
+                                           const weno_params_t* p, void* hip_stream)
+{
+    if (!srcs || !dsts || count < 1) return WENO_EINVAL;
+    if (count > WENO_NOALLOC_MAX_IMAGES) return WENO_ENOSPC;
+    int rc = batched_check(srcs, dsts, count, p);
+    if (rc) return rc;
+    void* ws = nullptr;
+    rc = noalloc_scratch(&ws);
+    if (rc) return rc;
+    // the plan validates everything before it writes the table into the
+    // scratch (one host-to-device copy, then a wait on the stream); the run
+    // clears the queue head with a kernel before the persistent launch
+    weno_batch_plan_t plan;
+    rc = weno_zoom2x_batched_plan(srcs, dsts, count, p, ws, kNoAllocScratchBytes, hip_stream, &plan);
     if (rc) return rc;
     return weno_zoom2x_batched_run(&plan, hip_stream);
 }

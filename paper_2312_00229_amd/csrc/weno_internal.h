@@ -22,16 +22,16 @@ struct BatchTable {
     int64_t params_offset;
 };
 
-__host__ __device__ inline size_t batch_jobs_offset() { return 256; }
-__host__ __device__ inline size_t batch_prefix_offset(int count)
+__host__ __device__ constexpr size_t batch_jobs_offset() { return 256; }
+__host__ __device__ constexpr size_t batch_prefix_offset(int count)
 {
     return batch_jobs_offset() + (size_t)count * sizeof(wz::FwdJob);
 }
-__host__ __device__ inline size_t batch_params_offset(int count)
+__host__ __device__ constexpr size_t batch_params_offset(int count)
 {
     return (batch_prefix_offset(count) + (size_t)(count + 1) * sizeof(int64_t) + 15) / 16 * 16;
 }
-__host__ __device__ inline size_t batch_table_bytes(int count)
+__host__ __device__ constexpr size_t batch_table_bytes(int count)
 {
     return (batch_params_offset(count) + (size_t)count * sizeof(wz::FwdParams) + 255) / 256 * 256;
 }

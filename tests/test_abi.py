@@ -115,6 +115,23 @@ def test_weight_sum_limit():
     assert _plan_status(_p(beta=5.0, keps=1e-8)) == _lib.WENO_EINVAL     # 2^137
 
 
+def test_batched_noalloc_errors():
+    L = _lib.lib()
+    src = (WenoTensor * 2)(_t(), _t(ptr=0x2000))
+    dst = (WenoTensor * 2)(_t(ptr=0x100000, h=8, w=10), _t(ptr=0x200000, h=8, w=10))
+    p = _p()
+    assert L.weno_zoom2x_batched_noalloc(src, dst, 0, ctypes.byref(p), None) == _lib.WENO_EINVAL
+    assert L.weno_zoom2x_batched_noalloc(None, dst, 2, ctypes.byref(p), None) == _lib.WENO_EINVAL
+    assert L.weno_zoom2x_batched_noalloc(src, dst, _lib.WENO_NOALLOC_MAX_IMAGES + 1, ctypes.byref(p),
+                                         None) == _lib.WENO_ENOSPC
+    assert L.weno_zoom2x_batched_noalloc(src, dst, 2, None, None) == _lib.WENO_EINVAL
+    bad = (WenoTensor * 2)(_t(ptr=0x100000, h=8, w=10), _t(ptr=0x200000, h=8, w=9))
+    assert L.weno_zoom2x_batched_noalloc(src, bad, 2, ctypes.byref(p), None) == _lib.WENO_EINVAL
+    overlap = (WenoTensor * 2)(_t(ptr=0x100000, h=8, w=10), _t(ptr=0x100000 + 64, h=8, w=10))
+    assert L.weno_zoom2x_batched_noalloc(src, overlap, 2, ctypes.byref(p), None) == _lib.WENO_EOVERLAP
+    assert "fixed scratch" in _lib.status_string(_lib.WENO_ENOSPC)
+
+
 def test_beta_zero_allows_zero_eps_validation():
     # beta = 0 gives equal weights, eps never enters; validation alone (a
     # shape error is planted so nothing is launched)
