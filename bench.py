@@ -83,6 +83,25 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
+def host_threads() -> int:
+    """OpenMP threads the C oracle runs with (OMP_NUM_THREADS, else all cores)."""
+    try:
+        return int(os.environ.get("OMP_NUM_THREADS", ""))
+    except ValueError:
+        return os.cpu_count() or 1
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(img_planar, budget_s=10.0):
     """The FP64 oracle on the headline frame, repeated for about `budget_s`
     seconds of host time; the mean rate over the repeats."""
@@ -97,28 +116,31 @@ def cpu_baseline(img_planar, budget_s=10.0):
         if dt >= budget_s:
             break
     H, W = img_planar.shape[-2:]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": round(runs * 4 * H * W / dt / 1e6, 3),
         "unit": "output Mpix/s",
-        "cores": cores,
+        "cores": host_threads(),
         "kind": "oracle",
         "sample": "the full %dx%d RGB frame, one doubling (3 planes), FP64 C oracle, OpenMP, %d repeats"
                   % (W, H, runs),
         "seconds": round(dt, 3),
+        "cpu_model": host_cpu_model(),
+        "logical_cpus": os.cpu_count(),
     }
 
 
 def cpu_baseline_others(batch_imgs):
-    """Bounded samples of the other workloads on the FP64 oracle, and the
-    headline frame's first plane on one thread (a few seconds in total)."""
+    """The FP64 oracle on each of the other workloads, whole: the cascade,
+    all 512 images of the batch, forward + hand adjoint of the 16x3x512x512
+    batch (the adjoint one plane per thread), and the headline frame's first
+    plane on one thread."""
     import ctypes
 
     import oracle
     from workloads import pixel_art, scene_rgb, to_planar_f32
 
     out = {}
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = host_threads()
     plane = to_planar_f32(scene_rgb(1080, 1920, seed=0))[0].astype(np.float64)
     try:
         gomp = ctypes.CDLL("libgomp.so.1")
@@ -137,24 +159,25 @@ def cpu_baseline_others(batch_imgs):
     dt = time.perf_counter() - t0
     out["cascade_256_x8"] = {"value": round(2048 * 2048 / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
                              "seconds": round(dt, 3), "sample": "the whole workload (3 levels, FP64 intermediates)"}
-    sample = batch_imgs[:16]
+    log("cpu baseline: 512 images ...")
     t0 = time.perf_counter()
-    for im in sample:
+    for im in batch_imgs:
         oracle.zoom2x(np.transpose(im, (2, 0, 1)).astype(np.float64) / 255.0)
     dt = time.perf_counter() - t0
-    opx = sum(4 * im.shape[0] * im.shape[1] for im in sample)
-    out["batched_16_of_512"] = {"value": round(opx / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
-                                "seconds": round(dt, 3), "sample": "the first 16 images of the 512"}
-    x = to_planar_f32(scene_rgb(512, 512, seed=100, n_polygons=20)).astype(np.float64)
-    g = np.random.default_rng(0).standard_normal((3, 1024, 1024))
+    opx = sum(4 * im.shape[0] * im.shape[1] for im in batch_imgs)
+    out["batched_512"] = {"value": round(opx / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
+                          "seconds": round(dt, 3), "sample": "all %d images" % len(batch_imgs)}
+    log("cpu baseline: forward + adjoint of 16x3x512x512 ...")
+    x = np.stack([to_planar_f32(scene_rgb(512, 512, seed=100 + i, n_polygons=20)) for i in range(16)]).astype(np.float64)
+    g = np.random.default_rng(0).standard_normal((16, 3, 1024, 1024))
     t0 = time.perf_counter()
     oracle.zoom2x(x)
-    for c in range(3):
-        oracle.backward(x[c], g[c])
+    oracle.backward(x, g)
     dt = time.perf_counter() - t0
-    out["fwd_bwd_1_of_16x3x512"] = {"value": round(1024 * 1024 / dt / 1e6, 3), "unit": "output Mpix/s", "cores": cores,
-                                    "seconds": round(dt, 3),
-                                    "sample": "one 3x512x512 image of the 16 (forward: OpenMP; hand adjoint: serial)"}
+    out["fwd_bwd_16x3x512"] = {"value": round(16 * 1024 * 1024 / dt / 1e6, 3), "unit": "output Mpix/s",
+                               "cores": cores, "seconds": round(dt, 3),
+                               "sample": "the whole batch (forward: OpenMP over rows; hand adjoint: one plane per "
+                                         "thread)"}
     return out
 
 
@@ -240,7 +263,16 @@ def main():
     import torch
 
     import paper_2312_00229_amd as wz
-    from workloads import batch_shapes, pixel_art, scene_rgb, to_planar_f32
+    from workloads import batch, batch_shapes, pixel_art, scene_rgb, to_planar_f32
+
+    special = args.only_u8 or args.only_fwd_bwd or args.only_zoom_to or args.only_main
+    if not special:
+        # the 512 uneven images (polygon scenes, seeds 2000 + i), generated in
+        # worker processes before anything touches the GPU
+        log("generating the 512 batch images ...")
+        t0 = time.perf_counter()
+        batch_imgs = batch(512, seed=2, workers=max(1, min(16, os.cpu_count() or 1)))
+        log("generated in %.1f s" % (time.perf_counter() - t0))
 
     assert torch.cuda.is_available(), "no GPU visible"
     dev = torch.device("cuda:0")
@@ -365,15 +397,8 @@ def main():
 
     # ---------------- batched: 512 uneven images ----------------
     shapes = batch_shapes(512, seed=2)
-    rng = np.random.default_rng(2)
-    bases = [scene_rgb(1024, 1024, seed=2000 + k, n_polygons=40) for k in range(8)]
-    imgs = []
-    for i, (h, w) in enumerate(shapes):
-        b = bases[i % len(bases)]
-        r0 = int(rng.integers(0, 1024 - h + 1))
-        c0 = int(rng.integers(0, 1024 - w + 1))
-        imgs.append(b[r0:r0 + h, c0:c0 + w])
-    xs = [torch.tensor(np.ascontiguousarray(im), device=dev).permute(2, 0, 1) for im in imgs]
+    imgs = batch_imgs
+    xs = [torch.tensor(im, device=dev).permute(2, 0, 1) for im in imgs]
     ys = [torch.empty((2 * h, 2 * w, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1) for (h, w) in shapes]
     # the persistent plan takes the autotuned strip shape (plans capture the
     # launch configuration when made); the per-image loop runs the plain
@@ -401,7 +426,7 @@ def main():
         "Mpix_per_s_launch_loop": round(bpx / (ms_l * 1e-3) / 1e6, 1),
         "tuned_launch": {"rows_per_strip": b_rows, "cols_per_lane": b_cols},
         "outputs_identical_to_loop": identical,
-        "content": "crops of eight 1024x1024 polygon scenes, sizes U{32..1024}^2 (seed 2)",
+        "content": "polygon scenes (seeds 2000 + i), sizes U{32..1024}^2 (seed 2)",
     }
     log("batched: persistent %.3f ms (rows %d, cols %d), loop %.3f ms, identical %s"
         % (ms_b, b_rows, b_cols, ms_l, identical))

@@ -5,7 +5,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libweno_zoom.so")
+# WENO_ZOOM_LIB: another build of the same library (e.g. a sanitizer build of
+# the host code for the ABI checks)
+LIB_PATH = os.environ.get("WENO_ZOOM_LIB") or os.path.join(_PKG, "libweno_zoom.so")
 
 WENO_OK = 0
 WENO_EINVAL = -1

@@ -55,5 +55,46 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_asan(out_dir: str, verbose: bool = False) -> str:
+    """The same library with AddressSanitizer on its HOST code only (device
+    code is built as usual), for the ABI checks on the CPU: the three sources
+    are compiled in parallel and linked into out_dir/libweno_zoom_asan.so.
+    Load it through WENO_ZOOM_LIB with the sanitizer runtime preloaded
+    (asan_runtime())."""
+    os.makedirs(out_dir, exist_ok=True)
+    common = [hipcc(), "--offload-arch=" + ARCH, "-O1", "-g", "-std=c++17", "-fPIC", "-fno-omit-frame-pointer",
+              "-Xarch_host", "-fsanitize=address",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
+              "-I" + INCLUDE, "-I" + CSRC]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(out_dir, src.replace(".hip", ".o"))
+        objs.append(obj)
+        procs.append(subprocess.Popen(common + ["-c", os.path.join(CSRC, src), "-o", obj],
+                                      stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+    for pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out)
+            raise RuntimeError("hipcc failed building the sanitizer objects")
+    lib = os.path.join(out_dir, "libweno_zoom_asan.so")
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address", *objs,
+           "-o", lib]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, capture_output=True)
+    return lib
+
+
+def asan_runtime() -> str:
+    """Path of the AddressSanitizer runtime of ROCm's clang."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    res = subprocess.run([clang, "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True,
+                         check=True)
+    return res.stdout.strip()
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

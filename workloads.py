@@ -135,12 +135,21 @@ def batch_shapes(count: int = 512, seed: int = 2, lo: int = 32, hi: int = 1024):
     return [(int(h), int(w)) for h, w in zip(hs, ws)]
 
 
-def batch(count: int = 512, seed: int = 2, lo: int = 32, hi: int = 1024, n_polygons: int = 40):
-    """Images of `batch_shapes`, content as `scene_rgb` with seed 1000*seed + i."""
-    return [
-        scene_rgb(h, w, seed=1000 * seed + i, n_polygons=n_polygons)
-        for i, (h, w) in enumerate(batch_shapes(count, seed, lo, hi))
-    ]
+def _scene_job(args):
+    h, w, seed, n_polygons = args
+    return scene_rgb(h, w, seed=seed, n_polygons=n_polygons)
+
+
+def batch(count: int = 512, seed: int = 2, lo: int = 32, hi: int = 1024, n_polygons: int = 40, workers: int = 1):
+    """Images of `batch_shapes`, content as `scene_rgb` with seed 1000*seed + i
+    (generated in `workers` processes when > 1; the same images either way)."""
+    jobs = [(h, w, 1000 * seed + i, n_polygons) for i, (h, w) in enumerate(batch_shapes(count, seed, lo, hi))]
+    if workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(_scene_job, jobs, chunksize=4))
+    return [_scene_job(j) for j in jobs]
 
 
 def to_planar_f32(img_u8: np.ndarray) -> np.ndarray:
