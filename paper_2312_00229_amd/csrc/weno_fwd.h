@@ -24,9 +24,15 @@
 //
 // Arithmetic (all FP32): for a stencil (a, b, c) on nodes -1, 1, 3 the
 // candidate is (a+b)/2 - dd/8 with dd = a - 2b + c, and the indicator
-// (b-a)^2 + 13/12 dd^2.  The kernel carries SI' = (12/13) SI: the common
-// factor cancels in the normalised weights.  eps is folded into every SI' as
-// eps_hat = eps*12/13 / (1 + 4w), so SI'_self + w * sum SI'_nbr = (12/13)(D + eps).
+// (b-a)^2 + 13/12 dd^2.  The doubling keeps two scaled copies of every sample
+// (input rows and x points): h = v/2 and s = kappa v with kappa^2 = 13/48.
+// Then (a+b)/2 = h_a + h_b, g = h_b - h_a = (b-a)/2, dds = s_a - 2 s_b + s_c
+// = kappa dd, and the kernel carries SI/4 = g^2 + dds^2: neither the 1/2 of
+// the mean nor the 13/12 of the indicator costs an instruction.  The common
+// factor 1/4 cancels in the normalised weights; eps is folded into every SI/4
+// as eps_q = eps / (4 (1 + 4w)), so SI/4_self + w * sum SI/4_nbr = (D + eps)/4.
+// (The adjoint carries SI' = (12/13) SI instead, with eps_hat = eps*12/13 /
+// (1 + 4w), so that SI'_self + w * sum SI'_nbr = (12/13)(D + eps).)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,7 +70,8 @@ constexpr bool io_scaled(int io) { return io == kIoU8F32 || io == kIoF32U8; }
 constexpr uint32_t kOob = 0x80000000u;
 
 struct FwdParams {
-    float eps_hat;  // see header comment, in the kernel's value scale
+    float eps_hat;  // adjoint: eps*12/13 / (1 + 4w), in the kernel's value scale
+    float eps_q;    // doubling: eps / (4 (1 + 4w)), in the kernel's value scale
     float w;        // neighbour-indicator weight
     float beta;     // used by the general-beta path
     float out_scale;  // output value = u * out_scale before quantisation
@@ -139,19 +146,32 @@ __device__ __forceinline__ float cand(float dd, float m) { return __builtin_fmaf
 __device__ __forceinline__ float sidx(float dd, float gc) { return __builtin_fmaf(dd, dd, gc); }
 // g^2 * 12/13 + eps_hat
 __device__ __forceinline__ float gterm(float g, float eps_hat) { return __builtin_fmaf(g * g, 12.0f / 13.0f, eps_hat); }
+
+// The doubling's scaled copies (see the header comment): h = v/2, s = kappa v
+constexpr float kKappa = 0.52041649986653320f;    // sqrt(13/48)
+constexpr float kCandS = -0.24019223070763074f;   // -1 / (8 kappa): dd/8 from dds
+__device__ __forceinline__ float half_of(float v) { return 0.5f * v; }
+__device__ __forceinline__ float kappa_of(float v) { return kKappa * v; }
+// candidate m - dd/8 from dds = kappa dd
+__device__ __forceinline__ float cand_s(float dds, float m) { return __builtin_fmaf(dds, kCandS, m); }
+// g^2 + eps_q from g = (b - a)/2
+__device__ __forceinline__ float gterm_q(float g, float eps_q) { return __builtin_fmaf(g, g, eps_q); }
 // a - 2b + c
 __device__ __forceinline__ float d2(float a, float b, float c) { return __builtin_fmaf(-2.0f, b, a + c); }
 
 template <int COLS>
 struct StripState {
-    // input rows R .. R+4 (row R+5 is loaded by the iteration)
+    // input rows R .. R+4 (row R+5 is loaded by the iteration): the samples
+    // (stored as the quads' originals) and their copies h = v/2, s = kappa v
     float V0[COLS], V1[COLS], V2[COLS], V3[COLS], V4[COLS];
+    float H0[COLS], H1[COLS], H2[COLS], H3[COLS], H4[COLS];
+    float S0[COLS], S1[COLS], S2[COLS], S3[COLS], S4[COLS];
     // main-diagonal second difference centred at (R+3, J); anti-diagonal at (R+3, J+1)
     float dd1_3[COLS], dd2s_3[COLS];
     // phase-1 scaled indicators at x rows R+1, R+2 and candidates at x row R+2
     float SX1[4][COLS], SX2[4][COLS], PX2[4][COLS];
-    // x values at rows R, R+1
-    float X0[COLS], X1[COLS];
+    // x values at rows R, R+1 and their copies x/2, kappa x
+    float X0[COLS], X1[COLS], XH0[COLS], XH1[COLS], XS0[COLS], XS1[COLS];
     // vertical second differences centred at row R: of x (X(R-1)-2X(R)+X(R+1)) and of V
     float ddXv0[COLS], ddr0[COLS];
     // phase-2: B(R) indicators/candidates, B pair sums at row R, A pair sums at row R-1
@@ -378,20 +398,24 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
     constexpr bool do_x = FULL || D >= -4;
     constexpr bool do_p2dd = FULL || D >= -2;
     constexpr bool do_p2 = FULL || D >= -1;
-    const float eh = P.eps_hat, w = P.w;
+    const float eq = P.eps_q, w = P.w;
 
-    float V5[COLS];
+    float V5[COLS], H5[COLS], S5[COLS];
 #pragma unroll
-    for (int c = 0; c < COLS; ++c) V5[c] = raw_value<IO>(cx, Q[c]);
+    for (int c = 0; c < COLS; ++c) {
+        V5[c] = raw_value<IO>(cx, Q[c]);
+        H5[c] = half_of(V5[c]);
+        S5[c] = kappa_of(V5[c]);
+    }
     load_row_raw<COLS, IO>(cx, L.src_off, R + 7, Q);
 
-    // ---- dd: diagonal second differences centred at (R+4, J) ----
+    // ---- dd: diagonal second differences (times kappa) centred at (R+4, J) ----
     float dd1_4[COLS] = {}, dd2_4[COLS] = {}, dd1s_4[COLS] = {}, dd2s_4[COLS] = {};
     if constexpr (do_dd) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            dd1_4[c] = d2(lft(s.V3, c), s.V4[c], rgt(V5, c));  // (R+3,J-1) (R+4,J) (R+5,J+1)
-            dd2_4[c] = d2(rgt(s.V3, c), s.V4[c], lft(V5, c));  // (R+3,J+1) (R+4,J) (R+5,J-1)
+            dd1_4[c] = d2(lft(s.S3, c), s.S4[c], rgt(S5, c));  // (R+3,J-1) (R+4,J) (R+5,J+1)
+            dd2_4[c] = d2(rgt(s.S3, c), s.S4[c], lft(S5, c));  // (R+3,J+1) (R+4,J) (R+5,J-1)
         }
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
@@ -409,19 +433,19 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
     if constexpr (do_sx) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            const float a1 = s.V3[c], b1 = rgt(s.V4, c);
-            const float a2 = rgt(s.V3, c), b2 = s.V4[c];
-            const float gc1 = gterm(b1 - a1, eh), gc2 = gterm(b2 - a2, eh);
-            const float m1 = 0.5f * (a1 + b1), m2 = 0.5f * (a2 + b2);
-            SX3[0][c] = sidx(dd1s_4[c], gc1);   PX3[0][c] = cand(dd1s_4[c], m1);
-            SX3[2][c] = sidx(s.dd1_3[c], gc1);  PX3[2][c] = cand(s.dd1_3[c], m1);
-            SX3[1][c] = sidx(s.dd2s_3[c], gc2); PX3[1][c] = cand(s.dd2s_3[c], m2);
-            SX3[3][c] = sidx(dd2_4[c], gc2);    PX3[3][c] = cand(dd2_4[c], m2);
+            const float a1 = s.H3[c], b1 = rgt(s.H4, c);
+            const float a2 = rgt(s.H3, c), b2 = s.H4[c];
+            const float gc1 = gterm_q(b1 - a1, eq), gc2 = gterm_q(b2 - a2, eq);
+            const float m1 = a1 + b1, m2 = a2 + b2;
+            SX3[0][c] = sidx(dd1s_4[c], gc1);   PX3[0][c] = cand_s(dd1s_4[c], m1);
+            SX3[2][c] = sidx(s.dd1_3[c], gc1);  PX3[2][c] = cand_s(s.dd1_3[c], m1);
+            SX3[1][c] = sidx(s.dd2s_3[c], gc2); PX3[1][c] = cand_s(s.dd2s_3[c], m2);
+            SX3[3][c] = sidx(dd2_4[c], gc2);    PX3[3][c] = cand_s(dd2_4[c], m2);
         }
     }
 
     // ---- x: D over the four same-direction neighbours (I+-1, J), (I, J+-1); blend X(R+2, J) ----
-    float X2[COLS] = {};
+    float X2[COLS] = {}, XH2[COLS] = {}, XS2[COLS] = {};
     if constexpr (do_x) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
@@ -432,6 +456,8 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
                 t[k] = __builtin_fmaf(w, ns, s.SX2[k][c]);
             }
             X2[c] = blend4<BETA>(t[0], t[1], t[2], t[3], s.PX2[0][c], s.PX2[1][c], s.PX2[2][c], s.PX2[3][c], P.beta);
+            XH2[c] = half_of(X2[c]);
+            XS2[c] = kappa_of(X2[c]);
         }
     }
 
@@ -440,8 +466,8 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
     if constexpr (do_p2dd) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            ddXv1[c] = d2(s.X0[c], s.X1[c], X2[c]);
-            ddr1[c] = d2(s.V0[c], s.V1[c], s.V2[c]);
+            ddXv1[c] = d2(s.XS0[c], s.XS1[c], XS2[c]);
+            ddr1[c] = d2(s.S0[c], s.S1[c], s.S2[c]);
         }
     }
 
@@ -449,35 +475,35 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
     float SB1[4][COLS] = {}, PB1[4][COLS] = {}, hB1[4][COLS] = {};
     float SA0[4][COLS] = {}, PA0[4][COLS] = {}, hA0[4][COLS] = {};
     if constexpr (do_p2) {
-        float v1r[COLS], ddc[COLS], x0l[COLS], ddXh[COLS];
+        float h1r[COLS], ddc[COLS], xh0l[COLS], ddXh[COLS];
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            v1r[c] = rgt(s.V1, c);
-            ddc[c] = d2(lft(s.V1, c), s.V1[c], v1r[c]);     // V row R+1, centred at J
-            x0l[c] = lft(s.X0, c);
-            ddXh[c] = d2(x0l[c], s.X0[c], rgt(s.X0, c));    // X row R, centred at J
+            h1r[c] = rgt(s.H1, c);
+            ddc[c] = d2(lft(s.S1, c), s.S1[c], rgt(s.S1, c));      // V row R+1, centred at J
+            xh0l[c] = lft(s.XH0, c);
+            ddXh[c] = d2(lft(s.XS0, c), s.XS0[c], rgt(s.XS0, c));  // X row R, centred at J
         }
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
             // B(R+1, J) at (R+1, J+1/2).  Vertical line through X(R,J), X(R+1,J):
-            const float gcv = gterm(s.X1[c] - s.X0[c], eh), mv = 0.5f * (s.X0[c] + s.X1[c]);
-            SB1[0][c] = sidx(ddXv1[c], gcv);   PB1[0][c] = cand(ddXv1[c], mv);    // X(R), X(R+1), X(R+2)
-            SB1[2][c] = sidx(s.ddXv0[c], gcv); PB1[2][c] = cand(s.ddXv0[c], mv);  // X(R+1), X(R), X(R-1)
+            const float gcv = gterm_q(s.XH1[c] - s.XH0[c], eq), mv = s.XH0[c] + s.XH1[c];
+            SB1[0][c] = sidx(ddXv1[c], gcv);   PB1[0][c] = cand_s(ddXv1[c], mv);    // X(R), X(R+1), X(R+2)
+            SB1[2][c] = sidx(s.ddXv0[c], gcv); PB1[2][c] = cand_s(s.ddXv0[c], mv);  // X(R+1), X(R), X(R-1)
             // horizontal line through V(R+1,J), V(R+1,J+1)
-            const float gch = gterm(v1r[c] - s.V1[c], eh), mh = 0.5f * (s.V1[c] + v1r[c]);
-            const float ddcs = rgt(ddc, c);                                        // centred at J+1
-            SB1[1][c] = sidx(ddcs, gch);       PB1[1][c] = cand(ddcs, mh);        // V(R+1,J..J+2)
-            SB1[3][c] = sidx(ddc[c], gch);     PB1[3][c] = cand(ddc[c], mh);      // V(R+1,J+1..J-1)
+            const float gch = gterm_q(h1r[c] - s.H1[c], eq), mh = s.H1[c] + h1r[c];
+            const float ddcs = rgt(ddc, c);                                          // centred at J+1
+            SB1[1][c] = sidx(ddcs, gch);       PB1[1][c] = cand_s(ddcs, mh);        // V(R+1,J..J+2)
+            SB1[3][c] = sidx(ddc[c], gch);     PB1[3][c] = cand_s(ddc[c], mh);      // V(R+1,J+1..J-1)
 
             // A(R, J) at (R+1/2, J).  Vertical line through V(R,J), V(R+1,J):
-            const float gav = gterm(s.V1[c] - s.V0[c], eh), mav = 0.5f * (s.V0[c] + s.V1[c]);
-            SA0[0][c] = sidx(ddr1[c], gav);    PA0[0][c] = cand(ddr1[c], mav);    // V(R), V(R+1), V(R+2)
-            SA0[2][c] = sidx(s.ddr0[c], gav);  PA0[2][c] = cand(s.ddr0[c], mav);  // V(R+1), V(R), V(R-1)
+            const float gav = gterm_q(s.H1[c] - s.H0[c], eq), mav = s.H0[c] + s.H1[c];
+            SA0[0][c] = sidx(ddr1[c], gav);    PA0[0][c] = cand_s(ddr1[c], mav);    // V(R), V(R+1), V(R+2)
+            SA0[2][c] = sidx(s.ddr0[c], gav);  PA0[2][c] = cand_s(s.ddr0[c], mav);  // V(R+1), V(R), V(R-1)
             // horizontal line through X(R,J-1), X(R,J)
-            const float gah = gterm(s.X0[c] - x0l[c], eh), mah = 0.5f * (x0l[c] + s.X0[c]);
-            const float ddXhl = lft(ddXh, c);                                      // centred at J-1
-            SA0[1][c] = sidx(ddXh[c], gah);    PA0[1][c] = cand(ddXh[c], mah);    // X(R,J-1..J+1)
-            SA0[3][c] = sidx(ddXhl, gah);      PA0[3][c] = cand(ddXhl, mah);      // X(R,J..J-2)
+            const float gah = gterm_q(s.XH0[c] - xh0l[c], eq), mah = xh0l[c] + s.XH0[c];
+            const float ddXhl = lft(ddXh, c);                                        // centred at J-1
+            SA0[1][c] = sidx(ddXh[c], gah);    PA0[1][c] = cand_s(ddXh[c], mah);    // X(R,J-1..J+1)
+            SA0[3][c] = sidx(ddXhl, gah);      PA0[3][c] = cand_s(ddXhl, mah);      // X(R,J..J-2)
         }
         // pair sums for the combined indicators of eq. (tezine):
         //   D_A(I,J) = SI_A(I,J) + w [SI_B(I,J-1) + SI_B(I,J) + SI_B(I+1,J-1) + SI_B(I+1,J)]
@@ -507,16 +533,34 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
             Bq[c] = blend4<BETA>(tb[0], tb[1], tb[2], tb[3], s.PB0[0][c], s.PB0[1][c], s.PB0[2][c],
                                  s.PB0[3][c], P.beta);
         }
-        if constexpr (IO == kIoGeneric) store_quads<COLS>(cx, R, L.J, L.own_all, L.own, s.V0, Bq, Aq, s.X0);
-        else store_quads_fixed<COLS, IO>(cx, R, L, s.V0, Bq, Aq, s.X0);
+        if constexpr (IO == kIoGeneric) {
+            store_quads<COLS>(cx, R, L.J, L.own_all, L.own, s.V0, Bq, Aq, s.X0);
+        } else if constexpr (io_out_u8(IO)) {
+            // byte outputs are rounded anyway: the originals and x values are
+            // rebuilt from their halves (exact for every normal float), so the
+            // raw windows are dead and the kernel keeps three waves per SIMD
+            float v0[COLS], x0[COLS];
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                v0[c] = s.H0[c] + s.H0[c];
+                x0[c] = s.XH0[c] + s.XH0[c];
+            }
+            store_quads_fixed<COLS, IO>(cx, R, L, v0, Bq, Aq, x0);
+        } else {
+            store_quads_fixed<COLS, IO>(cx, R, L, s.V0, Bq, Aq, s.X0);
+        }
     }
 
     // ---- slide the windows by one row ----
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         s.V0[c] = s.V1[c]; s.V1[c] = s.V2[c]; s.V2[c] = s.V3[c]; s.V3[c] = s.V4[c]; s.V4[c] = V5[c];
+        s.H0[c] = s.H1[c]; s.H1[c] = s.H2[c]; s.H2[c] = s.H3[c]; s.H3[c] = s.H4[c]; s.H4[c] = H5[c];
+        s.S0[c] = s.S1[c]; s.S1[c] = s.S2[c]; s.S2[c] = s.S3[c]; s.S3[c] = s.S4[c]; s.S4[c] = S5[c];
         s.dd1_3[c] = dd1_4[c]; s.dd2s_3[c] = dd2s_4[c];
         s.X0[c] = s.X1[c]; s.X1[c] = X2[c];
+        s.XH0[c] = s.XH1[c]; s.XH1[c] = XH2[c];
+        s.XS0[c] = s.XS1[c]; s.XS1[c] = XS2[c];
         s.ddXv0[c] = ddXv1[c]; s.ddr0[c] = ddr1[c];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -560,7 +604,10 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         s.V0[c] = s.V1[c] = s.V2[c] = s.V3[c] = s.V4[c] = 0.0f;
+        s.H0[c] = s.H1[c] = s.H2[c] = s.H3[c] = s.H4[c] = 0.0f;
+        s.S0[c] = s.S1[c] = s.S2[c] = s.S3[c] = s.S4[c] = 0.0f;
         s.dd1_3[c] = s.dd2s_3[c] = s.X0[c] = s.X1[c] = s.ddXv0[c] = s.ddr0[c] = 0.0f;
+        s.XH0[c] = s.XH1[c] = s.XS0[c] = s.XS1[c] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             // indicator windows start at 1 so that pipeline-fill blends never divide by zero
