@@ -89,3 +89,38 @@ def test_cascade_into_callers_output(gpu):
     assert torch.equal(out_f, ref_f)
     with pytest.raises(ValueError):
         gpu.zoom2x_cascade(x, 2, out=torch.empty((3, 148, 211), dtype=torch.uint8, device="cuda"))
+
+
+def _chain(gpu, x, levels, beta, out_dtype):
+    """The cascade as separate doublings through the public single-level call:
+    level l on spacing 2^-l (the default neighbour weight follows h^2/8)."""
+    cur = x
+    for lvl in range(levels):
+        last = lvl == levels - 1
+        cur = gpu.zoom2x(cur, gpu.Params(beta=beta, h=2.0 ** -lvl),
+                         out_dtype=(out_dtype if last else torch.float32))
+    return cur
+
+
+@pytest.mark.parametrize("levels,hw,beta", [(2, (40, 56), 2.0), (3, (32, 32), 2.0), (3, (21, 37), 1.0),
+                                            (4, (9, 13), 1.5), (3, (256, 256), 2.0), (2, (1, 70), 2.0)])
+def test_cascade_equals_separate_doublings(gpu, levels, hw, beta):
+    # the cascade (planar float32 intermediates in its workspace) against one
+    # public doubling per level with the spacing halved: bit-identical, for
+    # float32 and uint8 outputs
+    img = pixel_art(*hw, seed=3, block=4, n_lines=5)
+    x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    ws = torch.empty(gpu.cascade_workspace_bytes(x, levels), dtype=torch.uint8, device="cuda")
+    for out_dtype in (torch.float32, torch.uint8):
+        y = gpu.zoom2x_cascade(x, levels, gpu.Params(beta=beta), out_dtype=out_dtype, workspace=ws)
+        ref = _chain(gpu, x, levels, beta, out_dtype)
+        assert torch.equal(y, ref), (levels, hw, beta, out_dtype)
+
+
+def test_cascade_many_planes_f32(gpu):
+    rng = np.random.default_rng(4)
+    x = torch.tensor(rng.random((5, 3, 23, 130), dtype=np.float32), device="cuda")
+    ws = torch.empty(gpu.cascade_workspace_bytes(x, 3), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        y = gpu.zoom2x_cascade(x, 3, workspace=ws)
+        assert torch.equal(y, _chain(gpu, x, 3, 2.0, torch.float32))
