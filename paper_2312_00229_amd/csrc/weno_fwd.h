@@ -634,29 +634,19 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
     strip_step<COLS, BETA, IO, -2>(s, QB, cx, P, L, R0 - 2);
     strip_step<COLS, BETA, IO, -1>(s, QA, cx, P, L, R0 - 1);
     // Main walk, several rows per trip so that values carried from row to row
-    // are renamed rather than copied: six rows with two float columns per
-    // lane (the input window spans six rows and the x-point windows three, so
-    // all of them rotate by renaming alone), two otherwise.  The first trip
-    // is peeled: the loop is then entered only after the memory operations of
-    // a whole trip, as on every later trip, so the compiler's wait counts for
-    // the queued loads are exact rather than those of the store-free prologue.
-    // (The two loop forms below compute the same thing; each kernel family
-    // takes the one its register allocation handles best -- measured: the
-    // one-column kernels keep in-flight loads out of the back-edge copies in
-    // the plain form, the two-column byte kernels fit three waves per SIMD in
-    // the trip form.)
-    constexpr int TRIP = (COLS == 2 && !io_out_u8(IO) && IO != kIoGeneric) ? 6 : 2;
+    // are renamed rather than copied: six rows (the input windows span six
+    // rows and the x-point windows three, so all of them rotate by renaming
+    // alone), two for the runtime-flag path and for the two-column byte-output
+    // kernels (six-row trips would need over 256 VGPRs there: one wave per
+    // SIMD).  Measured VALU instructions per quad of the main loop: one
+    // column, six-row trips 164-174 against 178-185 for two-row trips.  The
+    // first trip is peeled: the loop is then entered only after the memory
+    // operations of a whole trip, as on every later trip, so the compiler's
+    // wait counts for the queued loads are exact rather than those of the
+    // store-free prologue.
+    constexpr int TRIP = (IO == kIoGeneric || (COLS == 2 && io_out_u8(IO))) ? 2 : 6;
     int R = R0;
-    if constexpr (COLS == 1) {
-        if (R + 1 < R1) {
-            strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
-            strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
-            for (R += 2; R + 1 < R1; R += 2) {
-                strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
-                strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
-            }
-        }
-    } else {
+    {
         auto trip = [&](int r) {
 #pragma unroll
             for (int k = 0; k < TRIP; k += 2) {
