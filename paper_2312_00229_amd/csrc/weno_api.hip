@@ -45,7 +45,7 @@ __device__ __forceinline__ StripCtx make_ctx(const FwdJob& jb, int n, int c, flo
     return cx;
 }
 
-template <int COLS, int BETA, int IO>
+template <int COLS, int BETA, int IO, bool PACED>
 __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
 {
     // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, 
     const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
     const int R0 = sy * rows_per_strip;
     const int R1 = min(R0 + rows_per_strip, jb.H);
-    zoom_strip<COLS, BETA, IO>(cx, P, sx, R0, R1);
+    zoom_strip<COLS, BETA, IO, PACED>(cx, P, sx, R0, R1);
 }
 
 // Persistent kernel over a work queue of strips of many images.  Item i of
@@ -370,19 +370,47 @@ int wz_check_pair(const weno_tensor_t* src, const weno_tensor_t* dst, int factor
     return WENO_OK;
 }
 
-template <int COLS, int IO>
-static hipError_t launch_fwd_io(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
+static int device_cus();
+
+// Workgroups of a kernel that one compute unit holds at once.  Cached per
+// kernel: it depends only on the kernel's registers and the architecture,
+// and the library is built for one architecture.
+template <int COLS, int BETA, int IO>
+static int fwd_resident_blocks()
+{
+    static std::atomic<int> cache{0};
+    int v = cache.load();
+    if (v == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &v, reinterpret_cast<const void*>(zoom2x_kernel<COLS, BETA, IO, true>), kBlock, 0) != hipSuccess ||
+            v <= 0)
+            v = 1;
+        cache.store(v);
+    }
+    return v;
+}
+
+// A launch whose workgroups all fit on the device at once (one round) is
+// paced (zoom_strip); one of several rounds is not.
+template <int COLS, int BETA, int IO>
+static hipError_t launch_fwd_beta(const FwdJob& jb, const FwdParams& P, int rows, hipStream_t st)
 {
     const int per_plane = jb.strips_x * jb.strips_y;
     dim3 grid((per_plane + kWavesPerBlock - 1) / kWavesPerBlock, jb.planes);
-    dim3 block(kBlock);
-    if (beta_mode == 2)
-        hipLaunchKernelGGL((zoom2x_kernel<COLS, 2, IO>), grid, block, 0, st, jb, P, rows);
-    else if (beta_mode == 1)
-        hipLaunchKernelGGL((zoom2x_kernel<COLS, 1, IO>), grid, block, 0, st, jb, P, rows);
+    const int64_t blocks = (int64_t)grid.x * grid.y;
+    if (blocks <= (int64_t)fwd_resident_blocks<COLS, BETA, IO>() * device_cus())
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, BETA, IO, true>), grid, dim3(kBlock), 0, st, jb, P, rows);
     else
-        hipLaunchKernelGGL((zoom2x_kernel<COLS, kBetaGeneral, IO>), grid, block, 0, st, jb, P, rows);
+        hipLaunchKernelGGL((zoom2x_kernel<COLS, BETA, IO, false>), grid, dim3(kBlock), 0, st, jb, P, rows);
     return hipGetLastError();
+}
+
+template <int COLS, int IO>
+static hipError_t launch_fwd_io(const FwdJob& jb, const FwdParams& P, int beta_mode, int rows, hipStream_t st)
+{
+    if (beta_mode == 2) return launch_fwd_beta<COLS, 2, IO>(jb, P, rows, st);
+    if (beta_mode == 1) return launch_fwd_beta<COLS, 1, IO>(jb, P, rows, st);
+    return launch_fwd_beta<COLS, kBetaGeneral, IO>(jb, P, rows, st);
 }
 
 template <int COLS>
@@ -397,61 +425,64 @@ static hipError_t launch_fwd_cols(const FwdJob& jb, const FwdParams& P, int beta
     }
 }
 
-// SIMDs of the current device (4 per compute unit), cached per device
-static int device_simds()
+// compute units of the current device, cached per device
+static int device_cus()
 {
     static std::atomic<int> cache[64];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
     int v = cache[dev].load();
     if (v == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-        v = 4 * cus;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
         cache[dev].store(v);
     }
     return v;
 }
 
-// Automatic launch configuration from a cost model of the strip walk.  A
-// launch takes about
-//   m x (rows + 8) x R(cols, m)
-// where m = ceil(waves / SIMDs) is the number of waves a SIMD runs (they are
-// independent and equally long), rows + 8 the iterations of one wave plus the
-// fixed cost of starting it (its launch and the 9-row pipeline fill, about 8
-// iterations' worth in the fit) and R(cols, m) the time of one iteration of
-// one of m waves sharing a SIMD,
-// measured on MI355X (one or two quad columns per lane; a lone wave is
-// latency-bound, several share the VALU).  Candidates are, for each column
-// count and each m = 1..8, the tallest strips that give at most m waves per
-// SIMD; the cheapest wins (fewer columns per lane only when strictly cheaper).
-// On planes of 64x64 .. 4096x4096 this picks within ~10 % of the best of a
-// sweep; at 1080p RGB it gives two columns and 27-row strips.
+// Automatic launch configuration from a cost model of the strip walk.  Four
+// strips (waves) make a workgroup, which runs on one compute unit, one wave
+// per SIMD.  A launch whose busiest compute unit runs m workgroups takes about
+//   m x (rows + 4) x R(cols, m)  microseconds,
+// where rows + 4 are the iterations of one wave plus the fixed cost of
+// starting it (its launch and the pipeline fill) and R(cols, m) the time of
+// one iteration of one of m waves sharing a SIMD (a compute unit holds three
+// two-column or five one-column workgroups at once: up to that, one paced
+// round; beyond it, several rounds).  m counts workgroups, not waves: one
+// compute unit given one workgroup more than the rest holds up the launch.
+// R is fitted (least squares on the log of the time) to 511 timed launches
+// on MI355X: 20 shapes from 1x64x64 to 3x2160x3840 and 48x512x512, both
+// column counts, the three shortest strips of each m = 1..8.  Candidates
+// are, for each column count and m = 1..8, the shortest strips that put at
+// most m workgroups on a compute unit; the cheapest wins.  On those shapes
+// the pick is within 6.2 % of the best measured launch (1080p RGB: two
+// columns, 27-row strips).
 static double iteration_cost(int cols, int64_t m)
 {
-    // microseconds per iteration, fitted to kernel traces of 64x64 .. 4096x4096
-    // planes at the launch shapes that fill 1..9 waves per SIMD
-    static const double one[4] = {0.47, 0.34, 0.325, 0.295};
-    static const double two[4] = {0.71, 0.58, 0.58, 0.55};
-    return (cols == 1 ? one : two)[m < 4 ? m - 1 : 3];
+    static const double one[8] = {0.421, 0.348, 0.319, 0.309, 0.302, 0.313, 0.308, 0.306};
+    static const double two[8] = {0.708, 0.589, 0.557, 0.581, 0.571, 0.563, 0.562, 0.578};
+    return (cols == 1 ? one : two)[m < 8 ? m - 1 : 7];
 }
+constexpr int kStartCost = 4;
 
 void wz_auto_config(int64_t planes, int H, int W, int* rows, int* cols)
 {
-    const int64_t simds = device_simds();
+    const int64_t cus = device_cus();
     double best = 0.0;
     int best_rows = 8, best_cols = 2;
     for (int c = 2; c >= 1; --c) {
         const int own = c == 1 ? kWave - 9 : 2 * kWave - 10;
-        const int64_t columns = planes * ((W + own - 1) / own);
+        const int64_t strips_x = (W + own - 1) / own;
         for (int64_t m = 1; m <= 8; ++m) {
-            int64_t bands = m * simds / columns;
+            // the most bands whose workgroups (planes x ceil(strips / 4)) fit m per compute unit
+            const int64_t per_plane = m * cus / planes;
+            int64_t bands = kWavesPerBlock * per_plane / strips_x;
             if (bands < 1) bands = 1;
             int r = (int)((H + bands - 1) / bands);
             r = r < 4 ? 4 : (r > 4096 ? 4096 : r);
-            const int64_t waves = columns * ((H + r - 1) / r);
-            const int64_t mm = (waves + simds - 1) / simds;
-            const double cost = (double)mm * (r + 8) * iteration_cost(c, mm);
+            const int64_t strips = strips_x * ((H + r - 1) / r);
+            const int64_t blocks = planes * ((strips + kWavesPerBlock - 1) / kWavesPerBlock);
+            const int64_t mm = (blocks + cus - 1) / cus;
+            const double cost = (double)mm * (r + kStartCost) * iteration_cost(c, mm);
             if (best == 0.0 || cost < best) {
                 best = cost;
                 best_rows = r;

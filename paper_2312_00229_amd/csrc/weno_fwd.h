@@ -211,19 +211,36 @@ __device__ __forceinline__ void buf_st_f32(float v, rsrc_t r, uint32_t voff, uin
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
 }
+// Cache policy of the vector stores of whole output rows in a launch of one
+// round of waves: device scope (the SC1 bit), so the line is written through
+// this XCD's L2 rather than held dirty in it.  The output is written once and
+// never read back by the launch; held dirty, it is written back only when the
+// launch ends, where every XCD's L2 is flushed before a dependent launch may
+// start, and that flush of up to 4 MB per XCD is time the launch adds after
+// its last wave (1080p RGB float32: 38.7 -> 36.4 us).  Longer launches keep
+// the default write-back policy: there the flush is a small part of the
+// launch, and a store written through completes later, which delays the
+// waits of the loads issued after it (3x4320x7680: 0.524 -> 0.544 ms
+// written through).  Byte stores always keep it: their lines are filled in
+// pieces by several waves, and writing every piece through costs far more
+// than the flush (uint8 HWC 1080p: 69.7 against 43.5 us).
+constexpr int kStRows = 16;
+
+template <int POLICY = 0>
 __device__ __forceinline__ void buf_st_f32x2(float a, float b, rsrc_t r, uint32_t voff, uint32_t soff)
 {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     u32x2 v = {__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, POLICY);
 }
+template <int POLICY = 0>
 __device__ __forceinline__ void buf_st_f32x4(float a, float b, float c, float d, rsrc_t r, uint32_t voff,
                                              uint32_t soff)
 {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     u32x4 v = {__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b), __builtin_bit_cast(uint32_t, c),
                __builtin_bit_cast(uint32_t, d)};
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, POLICY);
 }
 __device__ __forceinline__ void buf_st_u8(uint32_t v, rsrc_t r, uint32_t voff, uint32_t soff)
 {
@@ -289,7 +306,7 @@ __device__ __forceinline__ uint32_t quant_u8(float u) { return __builtin_amdgcn_
 // store the 2x2 quads of row R for this lane's columns: fixed layouts,
 // branch-free (lanes that own nothing store through kOob).  Mixed dtypes
 // scale by out_scale (255 or 1/255), as the runtime-flag path does.
-template <int COLS, int IO>
+template <int COLS, int IO, int ST>
 __device__ __forceinline__ void store_quads_fixed(const StripCtx& cx, int R, const StripLanes<COLS>& L,
                                                   const float (&o00)[COLS], const float (&o01)[COLS],
                                                   const float (&o10)[COLS], const float (&o11)[COLS])
@@ -308,15 +325,15 @@ __device__ __forceinline__ void store_quads_fixed(const StripCtx& cx, int R, con
     }
     if constexpr (!io_out_u8(IO)) {
         if constexpr (COLS == 2) {
-            buf_st_f32x4(a[0], b[0], a[1], b[1], cx.dst, L.st_vec, r0);
-            buf_st_f32x4(c[0], d[0], c[1], d[1], cx.dst, L.st_vec, r1);
+            buf_st_f32x4<ST>(a[0], b[0], a[1], b[1], cx.dst, L.st_vec, r0);
+            buf_st_f32x4<ST>(c[0], d[0], c[1], d[1], cx.dst, L.st_vec, r1);
             if (L.any_half) {
-                buf_st_f32x2(a[0], b[0], cx.dst, L.st_half, r0);
-                buf_st_f32x2(c[0], d[0], cx.dst, L.st_half, r1);
+                buf_st_f32x2<ST>(a[0], b[0], cx.dst, L.st_half, r0);
+                buf_st_f32x2<ST>(c[0], d[0], cx.dst, L.st_half, r1);
             }
         } else {
-            buf_st_f32x2(a[0], b[0], cx.dst, L.st_vec, r0);
-            buf_st_f32x2(c[0], d[0], cx.dst, L.st_vec, r1);
+            buf_st_f32x2<ST>(a[0], b[0], cx.dst, L.st_vec, r0);
+            buf_st_f32x2<ST>(c[0], d[0], cx.dst, L.st_vec, r1);
         }
     } else {  // one byte per output
 #pragma unroll
@@ -331,7 +348,7 @@ __device__ __forceinline__ void store_quads_fixed(const StripCtx& cx, int R, con
 }
 
 // store the 2x2 quads of row R for this lane's columns (any layout)
-template <int COLS>
+template <int COLS, int ST>
 __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int (&J)[COLS], bool own_all,
                                             const bool (&own)[COLS], const float (&o00)[COLS],
                                             const float (&o01)[COLS], const float (&o10)[COLS],
@@ -342,14 +359,14 @@ __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int
     if (!cx.out_u8 && cx.out_scale == 1.0f && COLS == 2 && cx.vec == 2 && own_all) {
         // same dtype in and out: no rescaling
         const uint32_t off = (uint32_t)(2 * J[0]) * 4u;
-        buf_st_f32x4(o00[0], o01[0], o00[COLS - 1], o01[COLS - 1], cx.dst, off, r0);
-        buf_st_f32x4(o10[0], o11[0], o10[COLS - 1], o11[COLS - 1], cx.dst, off, r1);
+        buf_st_f32x4<ST>(o00[0], o01[0], o00[COLS - 1], o01[COLS - 1], cx.dst, off, r0);
+        buf_st_f32x4<ST>(o10[0], o11[0], o10[COLS - 1], o11[COLS - 1], cx.dst, off, r1);
     } else if (!cx.out_u8) {
         const float s = cx.out_scale;
         if (COLS == 2 && cx.vec == 2 && own_all) {
             const uint32_t off = (uint32_t)(2 * J[0]) * 4u;
-            buf_st_f32x4(o00[0] * s, o01[0] * s, o00[COLS - 1] * s, o01[COLS - 1] * s, cx.dst, off, r0);
-            buf_st_f32x4(o10[0] * s, o11[0] * s, o10[COLS - 1] * s, o11[COLS - 1] * s, cx.dst, off, r1);
+            buf_st_f32x4<ST>(o00[0] * s, o01[0] * s, o00[COLS - 1] * s, o01[COLS - 1] * s, cx.dst, off, r0);
+            buf_st_f32x4<ST>(o10[0] * s, o11[0] * s, o10[COLS - 1] * s, o11[COLS - 1] * s, cx.dst, off, r1);
         } else if (cx.vec >= 1) {
 #pragma unroll
             for (int c = 0; c < COLS; ++c) {
@@ -387,8 +404,8 @@ __device__ __forceinline__ void store_quads(const StripCtx& cx, int R, const int
 // is stored); D < 0: prologue iteration R = R0 + D, where each stage only
 // runs once its results can feed an output row >= R0.  Q is the queue slot
 // holding input row R+5 (loaded two iterations earlier); it is refilled with
-// row R+7.
-template <int COLS, int BETA, int IO, int D>
+// row R+7.  ST: cache policy of the row stores.
+template <int COLS, int BETA, int IO, int D, int ST = 0>
 __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[COLS], const StripCtx& cx,
                                            const FwdParams& P, const StripLanes<COLS>& L, int R)
 {
@@ -534,7 +551,7 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
                                  s.PB0[3][c], P.beta);
         }
         if constexpr (IO == kIoGeneric) {
-            store_quads<COLS>(cx, R, L.J, L.own_all, L.own, s.V0, Bq, Aq, s.X0);
+            store_quads<COLS, ST>(cx, R, L.J, L.own_all, L.own, s.V0, Bq, Aq, s.X0);
         } else if constexpr (io_out_u8(IO)) {
             // byte outputs are rounded anyway: the originals and x values are
             // rebuilt from their halves (exact for every normal float), so the
@@ -545,9 +562,9 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
                 v0[c] = s.H0[c] + s.H0[c];
                 x0[c] = s.XH0[c] + s.XH0[c];
             }
-            store_quads_fixed<COLS, IO>(cx, R, L, v0, Bq, Aq, x0);
+            store_quads_fixed<COLS, IO, ST>(cx, R, L, v0, Bq, Aq, x0);
         } else {
-            store_quads_fixed<COLS, IO>(cx, R, L, s.V0, Bq, Aq, s.X0);
+            store_quads_fixed<COLS, IO, ST>(cx, R, L, s.V0, Bq, Aq, s.X0);
         }
     }
 
@@ -572,9 +589,13 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
 }
 
 // Walk one strip: columns [Jbase, Jbase + 64*COLS), output rows [R0, R1).
-template <int COLS, int BETA, int IO>
+// PACED: the launch runs as one round of waves (every wave resident from the
+// start): pace the waves that share a SIMD and write whole output rows
+// through the L2.
+template <int COLS, int BETA, int IO, bool PACED = false>
 __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
 {
+    constexpr int ST = PACED ? kStRows : 0;
     constexpr int SPAN = kWave * COLS;
     constexpr int HALO_L = 4;
     constexpr int OWN = (COLS == 1) ? SPAN - 9 : SPAN - 10;  // even for COLS = 2 (16-byte stores)
@@ -618,21 +639,33 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
         }
     }
 
+    // Pacing by wave priority.  In a launch of one round, two or three waves
+    // share each SIMD from start to end, and among waves of equal priority the
+    // SIMD issues for the oldest whenever it can: left alone, one wave of each
+    // pair runs far ahead and finishes early, and the SIMD spends the end of
+    // the launch on one latency-bound wave (1080p RGB: half the waves end at
+    // 20 us, the rest at 35.7).  A paced wave steps its priority down from 3
+    // to 0 as it passes each quarter of its rows, so the wave that has done
+    // less goes first and the waves of a SIMD keep pace and end together.
+    // Launches of several rounds are not paced: there, waves ending together
+    // would leave the next round's waves to start, and run, alone.
+    if constexpr (PACED) __builtin_amdgcn_s_setprio(3);
+
     // two queue slots used in turn, so that a row is read two iterations
     // after its load and a slot is never copied while its load is in flight
     raw_t<IO> QA[COLS], QB[COLS];
     load_row_raw<COLS, IO>(cx, L.src_off, R0 - 4, QA);
     load_row_raw<COLS, IO>(cx, L.src_off, R0 - 3, QB);
     // prologue: rows R0-9 .. R0-1 fill the pipeline (no stores)
-    strip_step<COLS, BETA, IO, -9>(s, QA, cx, P, L, R0 - 9);
-    strip_step<COLS, BETA, IO, -8>(s, QB, cx, P, L, R0 - 8);
-    strip_step<COLS, BETA, IO, -7>(s, QA, cx, P, L, R0 - 7);
-    strip_step<COLS, BETA, IO, -6>(s, QB, cx, P, L, R0 - 6);
-    strip_step<COLS, BETA, IO, -5>(s, QA, cx, P, L, R0 - 5);
-    strip_step<COLS, BETA, IO, -4>(s, QB, cx, P, L, R0 - 4);
-    strip_step<COLS, BETA, IO, -3>(s, QA, cx, P, L, R0 - 3);
-    strip_step<COLS, BETA, IO, -2>(s, QB, cx, P, L, R0 - 2);
-    strip_step<COLS, BETA, IO, -1>(s, QA, cx, P, L, R0 - 1);
+    strip_step<COLS, BETA, IO, -9, ST>(s, QA, cx, P, L, R0 - 9);
+    strip_step<COLS, BETA, IO, -8, ST>(s, QB, cx, P, L, R0 - 8);
+    strip_step<COLS, BETA, IO, -7, ST>(s, QA, cx, P, L, R0 - 7);
+    strip_step<COLS, BETA, IO, -6, ST>(s, QB, cx, P, L, R0 - 6);
+    strip_step<COLS, BETA, IO, -5, ST>(s, QA, cx, P, L, R0 - 5);
+    strip_step<COLS, BETA, IO, -4, ST>(s, QB, cx, P, L, R0 - 4);
+    strip_step<COLS, BETA, IO, -3, ST>(s, QA, cx, P, L, R0 - 3);
+    strip_step<COLS, BETA, IO, -2, ST>(s, QB, cx, P, L, R0 - 2);
+    strip_step<COLS, BETA, IO, -1, ST>(s, QA, cx, P, L, R0 - 1);
     // Main walk, several rows per trip so that values carried from row to row
     // are renamed rather than copied: six rows (the input windows span six
     // rows and the x-point windows three, so all of them rotate by renaming
@@ -647,27 +680,40 @@ __device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& 
     constexpr int TRIP = (IO == kIoGeneric || (COLS == 2 && io_out_u8(IO))) ? 2 : 6;
     int R = R0;
     {
+        const int q1 = R0 + (R1 - R0) / 4, q2 = R0 + (R1 - R0) / 2, q3 = R0 + 3 * (R1 - R0) / 4;
+        auto prio = [&](int r) {
+            if constexpr (PACED) {
+                if (r >= q3) __builtin_amdgcn_s_setprio(0);
+                else if (r >= q2) __builtin_amdgcn_s_setprio(1);
+                else if (r >= q1) __builtin_amdgcn_s_setprio(2);
+                else __builtin_amdgcn_s_setprio(3);
+            }
+        };
         auto trip = [&](int r) {
 #pragma unroll
             for (int k = 0; k < TRIP; k += 2) {
-                strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, r + k);
-                strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, r + k + 1);
+                strip_step<COLS, BETA, IO, 0, ST>(s, QB, cx, P, L, r + k);
+                strip_step<COLS, BETA, IO, 0, ST>(s, QA, cx, P, L, r + k + 1);
             }
         };
         if (R + TRIP - 1 < R1) {
+            prio(R);
             trip(R);
-            for (R += TRIP; R + TRIP - 1 < R1; R += TRIP) trip(R);
+            for (R += TRIP; R + TRIP - 1 < R1; R += TRIP) {
+                prio(R);
+                trip(R);
+            }
         }
 #pragma unroll
         for (int k = 2; k < TRIP; k += 2) {
             if (R + 1 < R1) {
-                strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
-                strip_step<COLS, BETA, IO, 0>(s, QA, cx, P, L, R + 1);
+                strip_step<COLS, BETA, IO, 0, ST>(s, QB, cx, P, L, R);
+                strip_step<COLS, BETA, IO, 0, ST>(s, QA, cx, P, L, R + 1);
                 R += 2;
             }
         }
     }
-    if (R < R1) strip_step<COLS, BETA, IO, 0>(s, QB, cx, P, L, R);
+    if (R < R1) strip_step<COLS, BETA, IO, 0, ST>(s, QB, cx, P, L, R);
 }
 
 }  // namespace wz

@@ -175,6 +175,44 @@ def test_launch_configs_bit_identical(gpu):
         assert np.array_equal(o, outs[0])
 
 
+def _blocks(planes, H, W, rows, cols):
+    own = 118 if cols == 2 else 55
+    strips = -(-W // own) * -(-H // rows)
+    return planes * -(-strips // 4)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8_hwc"])
+def test_paced_and_unpaced_launches_bit_identical(gpu, dtype):
+    # A launch whose workgroups all fit on the device at once runs paced (wave
+    # priorities, rows written through the L2); one of several rounds does
+    # not.  Same arithmetic, so the outputs must match bit for bit, and the
+    # oracle.  1080p RGB: 27-row two-column strips give 510 workgroups (one
+    # round: at most three per compute unit); 4-row strips give thousands.
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    img = scene_rgb(1080, 1920, seed=4, n_polygons=30)
+    if dtype == "f32":
+        x = _f32(to_planar_f32(img))
+    else:
+        x = torch.tensor(img, device="cuda").permute(2, 0, 1)
+    outs = {}
+    for cfg in [(27, 2), (4, 2), (4, 1), (0, 0)]:
+        _set(gpu, cfg)
+        outs[cfg] = gpu.zoom2x(x).cpu().numpy()
+    _set(gpu, (0, 0))
+    assert _blocks(3, 1080, 1920, 27, 2) <= 3 * cus
+    assert _blocks(3, 1080, 1920, 4, 2) > 3 * cus and _blocks(3, 1080, 1920, 4, 1) > 5 * cus
+    for cfg, o in outs.items():
+        assert np.array_equal(o, outs[(27, 2)]), cfg
+    # and the oracle on a band of rows across the first strip boundaries
+    planes = np.transpose(img, (2, 0, 1)).astype(np.float64) / 255.0
+    ref = oracle.window_zoom2x(planes, 20, 60, 100, 260)
+    got = outs[(4, 2)][:, 40:120, 200:520]
+    if dtype == "f32":
+        assert np.abs(got - ref).max() <= TOL
+    else:
+        check_u8(got, ref, "paced/unpaced u8 band")
+
+
 def test_full_size_1080p_sampled(gpu):
     # 1920 x 1080 RGB uint8 scene (and its planar float32 /255 version),
     # zoomed to 3840 x 2160 in the benchmark's launch configuration (the
