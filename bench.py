@@ -13,7 +13,7 @@ doublings of a 256x256 pixel-art image replayed from a HIP graph, zooming the
 frame to 5760x3240 (two doublings and the tensor resampler), and
 forward+backward of a 16x3x512x512 float32 batch.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main | --only-zoom-to]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main | --only-zoom-to | --only-u8 | --only-fwd-bwd | --only-cascade]
 """
 from __future__ import annotations
 
@@ -38,7 +38,8 @@ ALU_PEAK_PACKED_TFLOPS = 157.2864
 # algorithmic FP32 operations per output quad per channel (FMA = 2, rcp = 1):
 # x point 74, each + point 64, second differences of phase 2 12
 FLOPS_PER_QUAD = 214
-KERNEL_SOURCES = ["paper_2312_00229_amd/csrc/weno_fwd.h"]  # the forward kernel body
+KERNEL_SOURCES = ["paper_2312_00229_amd/csrc/weno_fwd.h",  # the forward kernel body
+                  "paper_2312_00229_amd/csrc/weno_api.hip"]  # its launch: grid, block map, strip shape
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zoom2x_rgb_f32_1080p.json")
 
 
@@ -224,6 +225,37 @@ def fwd_bwd_batch(torch, dev):
     return xb, gy, torch.empty_like(gy)
 
 
+def cascade_extra(wz, torch, dev, steps, warmup):
+    """256^2 RGB pixel art (uint8 HWC), three doublings to 2048^2 uint8 HWC
+    (float32 intermediates), from a HIP graph and launched directly."""
+    from workloads import pixel_art
+
+    pa = pixel_art(256, 256, seed=1)
+    xp = torch.tensor(pa, device=dev).permute(2, 0, 1)
+    ws = torch.empty(wz.cascade_workspace_bytes(xp, 3), dtype=torch.uint8, device=dev)
+    out = torch.empty((2048, 2048, 3), dtype=torch.uint8, device=dev).permute(2, 0, 1)
+
+    def casc():
+        wz.zoom2x_cascade(xp, 3, workspace=ws, out=out)
+
+    casc()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        casc()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        casc()
+    ms_g = timed(g.replay, steps, warmup, torch)
+    ms_e = timed(casc, steps, warmup, torch)
+    log("cascade: graph %.4f ms eager %.4f ms" % (ms_g, ms_e))
+    return {"ms_graph": round(ms_g, 5), "ms_eager": round(ms_e, 5),
+            "Mpix_per_s_graph": round(2048 * 2048 / (ms_g * 1e-3) / 1e6, 1),
+            "Mpix_per_s_eager": round(2048 * 2048 / (ms_e * 1e-3) / 1e6, 1)}
+
+
 def only_fwd_bwd(wz, torch, dev, steps, warmup):
     xb, gy, yb = fwd_bwd_batch(torch, dev)
 
@@ -251,6 +283,8 @@ def main():
                     help="time only the same 1080p frame as uint8 HWC -> uint8 HWC (for profilers)")
     ap.add_argument("--only-fwd-bwd", action="store_true",
                     help="time only forward + adjoint of the 16x3x512^2 float32 batch (for profilers)")
+    ap.add_argument("--only-cascade", action="store_true",
+                    help="time only the 256^2 pixel-art cascade of three doublings (for profilers)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
@@ -265,7 +299,7 @@ def main():
     import paper_2312_00229_amd as wz
     from workloads import batch, batch_shapes, pixel_art, scene_rgb, to_planar_f32
 
-    special = args.only_u8 or args.only_fwd_bwd or args.only_zoom_to or args.only_main
+    special = args.only_u8 or args.only_fwd_bwd or args.only_zoom_to or args.only_main or args.only_cascade
     if not special:
         # the 512 uneven images (polygon scenes, seeds 2000 + i), generated in
         # worker processes before anything touches the GPU
@@ -295,6 +329,9 @@ def main():
         return
     if args.only_fwd_bwd:
         print(json.dumps(only_fwd_bwd(wz, torch, dev, args.steps, min(args.warmup, 300))), flush=True)
+        return
+    if args.only_cascade:
+        print(json.dumps(cascade_extra(wz, torch, dev, args.steps, args.warmup)), flush=True)
         return
     if args.only_zoom_to:
         if args.copy_calib:
@@ -431,31 +468,7 @@ def main():
     log("batched: persistent %.3f ms (rows %d, cols %d), loop %.3f ms, identical %s"
         % (ms_b, b_rows, b_cols, ms_l, identical))
 
-    # ---------------- cascade: 256^2 pixel art, 3 doublings, HIP graph ----------------
-    pa = pixel_art(256, 256, seed=1)
-    xp = torch.tensor(pa, device=dev).permute(2, 0, 1)
-    ws = torch.empty(wz.cascade_workspace_bytes(xp, 3), dtype=torch.uint8, device=dev)
-    outc = [None]
-
-    def casc():
-        outc[0] = wz.zoom2x_cascade(xp, 3, workspace=ws)
-
-    casc()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        casc()
-    torch.cuda.current_stream().wait_stream(s)
-    with torch.cuda.graph(g):
-        res = wz.zoom2x_cascade(xp, 3, workspace=ws)
-    ms_g = timed(g.replay, args.steps, args.warmup, torch)
-    ms_e = timed(casc, args.steps, args.warmup, torch)
-    extras["cascade_256_x8_u8"] = {"ms_graph": round(ms_g, 5), "ms_eager": round(ms_e, 5),
-                                   "Mpix_per_s_graph": round(2048 * 2048 / (ms_g * 1e-3) / 1e6, 1)}
-    log("cascade: graph %.4f ms eager %.4f ms" % (ms_g, ms_e))
-    del res
+    extras["cascade_256_x8_u8"] = cascade_extra(wz, torch, dev, args.steps, args.warmup)
 
     extras["zoom_to_rgb_f32_1080p_to_5760x3240"] = zoom_to_extra(wz, torch, x, dev, max(20, args.steps // 10))
 

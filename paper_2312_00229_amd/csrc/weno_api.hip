@@ -659,10 +659,7 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
 template <int COLS>
 static hipError_t launch_batched_cols(const weno_batch_plan_t* plan, hipStream_t st)
 {
-    int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (cus <= 0) cus = 256;
+    const int cus = device_cus();
     const int64_t waves_needed = plan->total_items;
     int64_t blocks = (int64_t)cus * 4;  // up to 4 workgroups (16 waves) per CU
     const int64_t by_work = (waves_needed + kWavesPerBlock - 1) / kWavesPerBlock;
