@@ -181,15 +181,30 @@ __device__ __forceinline__ float blend_seed(const float (&t)[4], const float (&p
     return u;
 }
 
-// adjoint of one stencil: (ga, gb, gc) from the candidate seed gp, the
-// indicator seed gs, and the stencil's g = b - a and dd = a - 2b + c
-__device__ __forceinline__ void stencil_adj(float gp, float gs, float g, float dd, float& ga, float& gb, float& gc)
+// adjoint of the two stencils of one line: the forward one (x0, x1, x2) and
+// the backward one (x1, x0, x-1), with g = x1 - x0 (the forward stencil's;
+// the backward one's is -g) and their own second differences ddf, ddb.
+// Returns the gradients at x0 (s0 = ga_f + gb_b), x1 (s1 = gb_f + ga_b), x2
+// (cf) and x-1 (cb).  A stencil (a, b, c) with candidate seed gp and
+// indicator seed gs gives
+//   ga = 3/8 gp + gs (2 dd - (24/13) g),  gb = 3/4 gp + gs ((24/13) g - 4 dd),
+//   gc = -1/8 gp + 2 gs dd;
+// written per line rather than per stencil, the slope terms of the two
+// stencils fold into one product F = (24/13) g (gs_f + gs_b), and with
+// E = 2 gs dd
+//   s0 = 3/8 gp_f + 3/4 gp_b + E_f - 2 E_b - F
+//   s1 = 3/4 gp_f + 3/8 gp_b - 2 E_f + E_b + F
+//   cf = -1/8 gp_f + E_f,   cb = -1/8 gp_b + E_b
+// (15 operations against 20 for two stencils and the two sums).
+__device__ __forceinline__ void line_adj(float gpf, float gsf, float ddf, float gpb, float gsb, float ddb, float g,
+                                         float& s0, float& s1, float& cf, float& cb)
 {
-    const float e = gs * dd;                         // half of dSI'/dc times gs
-    const float f = gs * (g * (24.0f / 13.0f));
-    ga = __builtin_fmaf(gp, 0.375f, __builtin_fmaf(e, 2.0f, -f));
-    gb = __builtin_fmaf(gp, 0.75f, __builtin_fmaf(e, -4.0f, f));
-    gc = __builtin_fmaf(gp, -0.125f, 2.0f * e);
+    const float ef = 2.0f * (gsf * ddf), eb = 2.0f * (gsb * ddb);
+    const float F = (gsf + gsb) * (g * (24.0f / 13.0f));
+    s0 = __builtin_fmaf(gpf, 0.375f, __builtin_fmaf(gpb, 0.75f, __builtin_fmaf(eb, -2.0f, ef - F)));
+    s1 = __builtin_fmaf(gpf, 0.75f, __builtin_fmaf(gpb, 0.375f, __builtin_fmaf(ef, -2.0f, eb + F)));
+    cf = __builtin_fmaf(gpf, -0.125f, ef);
+    cb = __builtin_fmaf(gpb, -0.125f, eb);
 }
 
 typedef float bwd_f32x4 __attribute__((ext_vector_type(4)));
@@ -328,7 +343,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             float t[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float ns = (SX1[k] + SX3[k]) + (nbL(SX2[k]) + nbR(SX2[k]));
+                // one neighbour shift per addition, so each folds into it (DPP operand)
+                const float ns = ((SX1[k] + SX3[k]) + nbL(SX2[k])) + nbR(SX2[k]);
                 t[k] = __builtin_fmaf(w, ns, SX2[k]);
             }
             X2 = blend_seed<BETA>(t, PX2, beta, omX2, dkX2);
@@ -419,41 +435,37 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         // ======================= phase-2 adjoint =======================
         {
             // A(s-1): indicator seeds gS = gt_A(s-1) + w [gt_B box over rows s-1, s, cols J-1, J]
-            float ga[4], gb[4], gc[4];
+            float gs[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float gs = __builtin_fmaf(w, qB_m1[k] + qB[k], gtA_m1[k]);
-                const float g = (k == 0) ? geoA_gv : (k == 2) ? -geoA_gv : (k == 1) ? geoA_gh : -geoA_gh;
-                const float dd = (k == 0) ? geoA_ddd : (k == 2) ? geoA_ddu : (k == 1) ? geoA_ddr : geoA_ddl;
-                stencil_adj(gpA_m1[k], gs, g, dd, ga[k], gb[k], gc[k]);
-            }
+            for (int k = 0; k < 4; ++k) gs[k] = __builtin_fmaf(w, qB_m1[k] + qB[k], gtA_m1[k]);
+            float s0, s1, cf, cb;
             // vertical stencils on V column J: k0 (V(s-1), V(s), V(s+1)), k2 (V(s), V(s-1), V(s-2))
-            accV_m1 += ga[0] + gb[2];
-            accV_0 += gb[0] + ga[2];
-            accV_p1 += gc[0];
-            accV_m2 += gc[2];
+            line_adj(gpA_m1[0], gs[0], geoA_ddd, gpA_m1[2], gs[2], geoA_ddu, geoA_gv, s0, s1, cf, cb);
+            accV_m1 += s0;
+            accV_0 += s1;
+            accV_p1 += cf;
+            accV_m2 += cb;
             // horizontal stencils on x row s-1: k1 (x[J-1], x[J], x[J+1]), k3 (x[J], x[J-1], x[J-2])
-            const float u = ga[1] + gb[3] + nbR(gc[3]);
-            accX_m1 += (gb[1] + ga[3]) + (nbR(u) + nbL(gc[1]));
+            line_adj(gpA_m1[1], gs[1], geoA_ddr, gpA_m1[3], gs[3], geoA_ddl, geoA_gh, s0, s1, cf, cb);
+            const float u = s0 + nbR(cb);
+            accX_m1 += (s1 + nbR(u)) + nbL(cf);
         }
         {
             // B(s): gS = gt_B(s) + w [gt_A box over rows s-1, s, cols J, J+1]
-            float ga[4], gb[4], gc[4];
+            float gs[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float gs = __builtin_fmaf(w, qA_m1[k] + qA[k], gtB[k]);
-                const float g = (k == 0) ? geoB_gv : (k == 2) ? -geoB_gv : (k == 1) ? geoB_gh : -geoB_gh;
-                const float dd = (k == 0) ? geoB_ddd : (k == 2) ? geoB_ddu : (k == 1) ? geoB_ddr : geoB_ddl;
-                stencil_adj(gpB[k], gs, g, dd, ga[k], gb[k], gc[k]);
-            }
+            for (int k = 0; k < 4; ++k) gs[k] = __builtin_fmaf(w, qA_m1[k] + qA[k], gtB[k]);
+            float s0, s1, cf, cb;
             // vertical stencils on x column J: k0 (x(s-1), x(s), x(s+1)), k2 (x(s), x(s-1), x(s-2))
-            accX_m1 += ga[0] + gb[2];
-            accX_0 += gb[0] + ga[2];
-            accX_p1 += gc[0];
-            accX_m2 += gc[2];
+            line_adj(gpB[0], gs[0], geoB_ddd, gpB[2], gs[2], geoB_ddu, geoB_gv, s0, s1, cf, cb);
+            accX_m1 += s0;
+            accX_0 += s1;
+            accX_p1 += cf;
+            accX_m2 += cb;
             // horizontal stencils on V row s: k1 (V[J], V[J+1], V[J+2]), k3 (V[J+1], V[J], V[J-1])
-            const float v = gb[1] + ga[3] + nbL(gc[1]);
-            accV_0 += (ga[1] + gb[3]) + (nbL(v) + nbR(gc[3]));
+            line_adj(gpB[1], gs[1], geoB_ddr, gpB[3], gs[3], geoB_ddl, geoB_gh, s0, s1, cf, cb);
+            const float v = s1 + nbL(cf);
+            accV_0 += (s0 + nbL(v)) + nbR(cb);
         }
 
         // ======================= phase-1 seeds at x row s-2 =======================
@@ -473,20 +485,19 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             const float dd2_r1 = d2(nbR(Qv), Rv, nbL(Tv));
             const float g1 = nbR(Rv) - Qv;         // V(r+1)[J+1] - V(r)[J]
             const float g2 = Rv - nbR(Qv);         // V(r+1)[J] - V(r)[J+1]
-            float ga[4], gb[4], gc[4];
+            float gs[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float gs = __builtin_fmaf(w, (gtX_m4[k] + gtX_m2[k]) + (nbL(gtX_m3[k]) + nbR(gtX_m3[k])), gtX_m3[k]);
-                const float g = (k == 0) ? g1 : (k == 2) ? -g1 : (k == 1) ? -g2 : g2;
-                const float dd = (k == 0) ? dd1s_r1 : (k == 2) ? dd1_r : (k == 1) ? dd2s_r : dd2_r1;
-                stencil_adj(gpX_m3[k], gs, g, dd, ga[k], gb[k], gc[k]);
-            }
+            for (int k = 0; k < 4; ++k)
+                gs[k] = __builtin_fmaf(w, ((gtX_m4[k] + gtX_m2[k]) + nbL(gtX_m3[k])) + nbR(gtX_m3[k]), gtX_m3[k]);
             // k0 (V(r)[J], V(r+1)[J+1], V(r+2)[J+2])   k2 (V(r+1)[J+1], V(r)[J], V(r-1)[J-1])
             // k1 (V(r+1)[J], V(r)[J+1], V(r-1)[J+2])   k3 (V(r)[J+1], V(r+1)[J], V(r+2)[J-1])
-            accV_m4 += nbR(gc[2]) + nbL(nbL(gc[1]));
-            accV_m3 += (ga[0] + gb[2]) + nbL(gb[1] + ga[3]);
-            accV_m2 += (ga[1] + gb[3]) + nbL(gb[0] + ga[2]);
-            accV_m1 += nbL(nbL(gc[0])) + nbR(gc[3]);
+            float d0, d1, d0c, d0b, a0, a1, a1c, a1b;
+            line_adj(gpX_m3[0], gs[0], dd1s_r1, gpX_m3[2], gs[2], dd1_r, g1, d0, d1, d0c, d0b);   // main diagonal
+            line_adj(gpX_m3[1], gs[1], dd2s_r, gpX_m3[3], gs[3], dd2_r1, -g2, a0, a1, a1c, a1b);  // anti-diagonal
+            accV_m4 += nbR(d0b) + nbL(nbL(a1c));
+            accV_m3 += d0 + nbL(a1);
+            accV_m2 += a0 + nbL(d1);
+            accV_m1 += nbL(nbL(d0c)) + nbR(a1b);
         }
 
         // ======================= dL/dV row s-4 is complete =======================
