@@ -213,6 +213,24 @@ def test_paced_and_unpaced_launches_bit_identical(gpu, dtype):
         check_u8(got, ref, "paced/unpaced u8 band")
 
 
+def test_interleaved_and_planar_layouts_bit_identical(gpu):
+    # HWC images launch on a grid padded to a multiple of the XCD count (the
+    # same strip of every channel on one XCD) and take their own strip height
+    # from the cost model; planar copies of the same data do neither.  Same
+    # arithmetic per plane, so the results must match bit for bit.
+    _set(gpu, (0, 0))
+    for (h, w) in [(1080, 1920), (333, 517), (64, 4000)]:
+        img = scene_rgb(h, w, seed=h + w, n_polygons=12)
+        hwc = torch.tensor(img, device="cuda").permute(2, 0, 1)
+        planar = hwc.contiguous()
+        a = gpu.zoom2x(hwc).cpu().numpy()
+        b = gpu.zoom2x(planar).cpu().numpy()
+        assert np.array_equal(a, b), (h, w)
+        af = gpu.zoom2x(hwc, out_dtype=torch.float32).cpu().numpy()
+        bf = gpu.zoom2x(planar, out_dtype=torch.float32).cpu().numpy()
+        assert np.array_equal(af, bf), (h, w)
+
+
 def test_full_size_1080p_sampled(gpu):
     # 1920 x 1080 RGB uint8 scene (and its planar float32 /255 version),
     # zoomed to 3840 x 2160 in the benchmark's launch configuration (the
