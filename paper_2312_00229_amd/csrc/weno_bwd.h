@@ -21,13 +21,15 @@
 // and the result is deterministic.  Iteration s:
 //   forward     the forward pipeline (rows up to s+5), blends of A(s), B(s)
 //               and x(s+2) keep the weight factors the seeds need (those of
-//               x(s+2) wait in LDS until iteration s+4);
+//               x(s+2) wait in LDS until iteration s+4, the diagonal second
+//               differences of input row s+4 until iterations s+6, s+7);
 //   seeds       phase-2 seeds of A(s), B(s) from dL/dU;
 //   p2 adjoint  indicator adjoints of A(s-1) and B(s); stencil adjoints into
 //               dL/dx (rows s-2..s+1) and dL/dV (rows s-2..s+1);
 //   p1 seeds    dL/dx of row s-2 is complete: seeds of x(s-2);
 //   p1 adjoint  indicator adjoints of x(s-3); stencil adjoints into dL/dV
-//               rows s-4..s-1 (input rows s-4..s-1 held in a register window);
+//               rows s-4..s-1 (the slopes from input rows s-3, s-2 held in a
+//               register window, the second differences from LDS);
 //   output      dL/dV row s-4 is complete: fold clamped rows/columns onto the
 //               edge pixels and store.
 // Valid lanes shrink with every neighbour access: the dL/dV of lanes 9..54 is
@@ -209,9 +211,12 @@ __device__ __forceinline__ void line_adj(float gpf, float gsf, float ddf, float 
 
 typedef float bwd_f32x4 __attribute__((ext_vector_type(4)));
 
-// LDS of one wave for the x-point seed factors: 4 slots (a row each) x
-// (omega_k, dk_k) x 64 lanes of 4 floats
-constexpr int kBwdRingWords = 4 * 2 * kWave;
+// LDS of one wave: the x-point seed factors, 4 slots (a row each) x
+// (omega_k, dk_k) x 64 lanes of 4 floats, then the diagonal second
+// differences of the input rows, 8 slots (a row each) x 64 lanes of 4 floats
+constexpr int kBwdSeedWords = 4 * 2 * kWave;
+constexpr int kBwdRingWords = kBwdSeedWords + 8 * kWave;
+typedef float bwd_f32x2 __attribute__((ext_vector_type(2)));
 
 template <int BETA>
 __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, int strip_x, int R0, int R1,
@@ -251,7 +256,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     auto stG = [&](int r, float val) { buf_st_f32(val, cx.gx, gxoff, (uint32_t)r * cx.gx_h); };
 
     // ---------------- forward state (rows relative to s) ----------------
-    float Vm4 = 0, Vm3 = 0, Vm2 = 0, Vm1 = 0;           // V(s-4) .. V(s-1)
+    float Vm3 = 0, Vm2 = 0, Vm1 = 0;                    // V(s-3) .. V(s-1)
     float V0 = 0, V1 = 0, V2 = 0, V3 = 0, V4 = 0;       // V(s) .. V(s+4)
     float dd1_3 = 0, dd2s_3 = 0;
     // indicator windows start at 1 so that pipeline-fill blends never divide by zero
@@ -267,6 +272,14 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // and then overwrites it with its own (each lane reads and writes only its
     // own words, so program order is all the ordering needed).
     auto ring_at = [&](int s, int half) -> bwd_f32x4& { return ring[((s & 3) * 2 + half) * kWave + lane]; };
+    // The diagonal second differences of input row r, {dd1, dd2s, dd1s, dd2}
+    // (dd1, dd2 centred at (r, J), dd1s, dd2s at (r, J+1)), made when row r
+    // enters the pipeline (step r-4) and read by the phase-1 adjoints of
+    // steps r+2 (the .zw half) and r+3 (the .xy half); slot r & 7 is next
+    // written at step r+4.
+    auto dd_at = [&](int r, int half) -> bwd_f32x2& {
+        return reinterpret_cast<bwd_f32x2*>(ring + kBwdSeedWords + (r & 7) * kWave + lane)[half];
+    };
     // ---------------- adjoint state ----------------
     float gtA_m1[4] = {}, gpA_m1[4] = {}, qA_m1[4] = {}, qB_m1[4] = {};
     float accX_m2 = 0, accX_m1 = 0, accX_0 = 0;          // dL/dx rows s-2, s-1, s
@@ -308,6 +321,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         Q1 = ldV(s + 7);
         float gA = 0, gB = 0, gXu = 0, gVu = 0;
         bwd_f32x4 omXr = {}, dkXr = {};   // seed factors of x row s-2
+        // second differences of input rows s-3 (.xy) and s-2 (.zw) for the
+        // phase-1 adjoint, read before this step writes row s+4's slot
+        bwd_f32x2 ddm3 = {}, ddm2 = {};
+        if constexpr (P1) {
+            ddm3 = dd_at(s - 3, 0);
+            ddm2 = dd_at(s - 2, 1);
+        }
         if constexpr (FULL) {
             omXr = ring_at(s, 0);
             dkXr = ring_at(s, 1);
@@ -324,6 +344,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             dd2_4 = d2(nbR(V3), V4, nbL(V5));
             dd1s_4 = nbR(dd1_4);
             dd2s_4 = nbR(dd2_4);
+            dd_at(s + 4, 0) = bwd_f32x2{dd1_4, dd2s_4};
+            dd_at(s + 4, 1) = bwd_f32x2{dd1s_4, dd2_4};
         }
         // x row s+3
         float SX3[4] = {1, 1, 1, 1}, PX3[4] = {};
@@ -478,11 +500,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
 
         // ======================= phase-1 adjoint at x row r = s-3 =======================
         if constexpr (P1) {
-            const float Pv = Vm4, Qv = Vm3, Rv = Vm2, Tv = Vm1;
-            const float dd1_r = d2(nbL(Pv), Qv, nbR(Rv));
-            const float dd1s_r1 = nbR(d2(nbL(Qv), Rv, nbR(Tv)));
-            const float dd2s_r = nbR(d2(nbR(Pv), Qv, nbL(Rv)));
-            const float dd2_r1 = d2(nbR(Qv), Rv, nbL(Tv));
+            const float Qv = Vm3, Rv = Vm2;
+            const float dd1_r = ddm3.x, dd2s_r = ddm3.y, dd1s_r1 = ddm2.x, dd2_r1 = ddm2.y;
             const float g1 = nbR(Rv) - Qv;         // V(r+1)[J+1] - V(r)[J]
             const float g2 = Rv - nbR(Qv);         // V(r+1)[J] - V(r)[J+1]
             float gs[4];
@@ -530,7 +549,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         }   // FULL
 
         // ======================= slide the windows =======================
-        Vm4 = Vm3; Vm3 = Vm2; Vm2 = Vm1; Vm1 = V0;
+        Vm3 = Vm2; Vm2 = Vm1; Vm1 = V0;
         V0 = V1; V1 = V2; V2 = V3; V3 = V4; V4 = V5;
         dd1_3 = dd1_4; dd2s_3 = dd2s_4;
         X0 = X1; X1 = X2; ddXv0 = ddXv1; ddr0 = ddr1;
