@@ -347,7 +347,7 @@ def main():
     alg_flops = FLOPS_PER_QUAD * 3 * H * W
     tflops = alg_flops / (ms * 1e-3) / 1e12
     traffic = measured_traffic()
-    rows, cols = wz.get_launch_config()
+    rows, cols, tail = wz.launch_shape(x)
     result = {
         "metric": "output Mpix/s + % HBM roofline (2x WENO zoom, RGB fp32); fwd+bwd Mpix/s",
         "value": round(value, 1),
@@ -363,7 +363,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "zoom2x 1920x1080 RGB fp32 planar -> 3840x2160, polygon scene (seed 0)",
-            "launch": {"rows_per_strip": rows, "cols_per_lane": cols},
+            "launch": {"rows_per_strip": rows, "cols_per_lane": cols, "tail_rows": tail},
         },
         "roofline": {
             "bound": "alu",

@@ -241,17 +241,33 @@ int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t* grad_y, co
  *   rows_per_strip: output rows one wave walks down, in [4, 4096]
  *   cols_per_lane:  1 or 2 columns of quads per lane
  * (0, 0) selects the automatic choice (the default): the columns per lane and
- * strip height that minimise a cost model of the launch (waves per SIMD x
- * iterations per wave x measured time per iteration); e.g. two columns and
- * 27-row strips for a 1920x1080 RGB frame, one column and 4-row strips for a
- * 256x256 one.  The configuration changes speed only: every
- * configuration produces bit-identical outputs.  Batched plans capture the
- * configuration when they are made (automatic: 32 rows, 2 columns).
+ * strip height that minimise a cost model of the launch (workgroups per
+ * compute unit x iterations per wave x measured time per iteration); e.g.
+ * two columns and 27-row strips for a 1920x1080 RGB frame, one column and
+ * 4-row strips for a 256x256 one.  For planar images whose last strip column
+ * would hold no more than a one-column strip owns (e.g. 512 wide: four
+ * two-column strips and 40 columns), the automatic choice may walk that
+ * column in one-column strips of taller bands ("tail" strips).  The
+ * configuration changes speed only: every configuration produces
+ * bit-identical outputs.  Batched plans capture the configuration when they
+ * are made (automatic: 32 rows, 2 columns, no tail strips).
  * weno_get_launch_config reports (0, 0) in automatic mode.
  * Returns WENO_EINVAL for values outside these sets.
  */
 int weno_set_launch_config(int32_t rows_per_strip, int32_t cols_per_lane);
 void weno_get_launch_config(int32_t* rows_per_strip, int32_t* cols_per_lane);
+
+/*
+ * The launch shape weno_zoom2x would use for this pair (the configuration
+ * set above, else the automatic choice): rows_per_strip, cols_per_lane and
+ * tail_rows (rows of the one-column tail strips; 0: none).  dst may be null:
+ * an output in src's layout is assumed (only the layouts matter; no memory
+ * is touched).  Any of the three out-pointers may be null.  Returns
+ * WENO_EINVAL for an invalid src, or a dst whose shape is not src's doubled;
+ * calls no HIP function but the current device and its attribute queries.
+ */
+int weno_query_launch_config(const weno_tensor_t* src, const weno_tensor_t* dst, int32_t* rows_per_strip,
+                             int32_t* cols_per_lane, int32_t* tail_rows);
 
 /*
  * Strip height of the adjoint kernel (weno_zoom2x_backward; process-global,

@@ -366,6 +366,18 @@ def get_launch_config():
     return int(r.value), int(c.value)
 
 
+def launch_shape(x: torch.Tensor) -> tuple:
+    """(rows_per_strip, cols_per_lane, tail_rows) that zoom2x(x) would launch
+    with into an output in x's layout (the configuration set by
+    set_launch_config, else the automatic one; tail_rows 0: no one-column
+    tail strips)."""
+    r, c, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    s = _desc(x)
+    _lib.check(_lib.lib().weno_query_launch_config(ctypes.byref(s), None, ctypes.byref(r), ctypes.byref(c),
+                                                   ctypes.byref(t)), "weno_query_launch_config")
+    return int(r.value), int(c.value), int(t.value)
+
+
 def set_backward_launch_config(rows_per_strip: int):
     """Strip height of the adjoint kernel (0 = automatic)."""
     _lib.check(_lib.lib().weno_set_backward_launch_config(int(rows_per_strip)), "weno_set_backward_launch_config")

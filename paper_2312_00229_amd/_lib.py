@@ -83,6 +83,8 @@ _SIGS = {
     "weno_zoom_to": (_I, [_T, _T, _P, _V, ctypes.c_size_t, _V]),
     "weno_set_launch_config": (_I, [ctypes.c_int32, ctypes.c_int32]),
     "weno_get_launch_config": (None, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "weno_query_launch_config": (_I, [_T, _T, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]),
     "weno_set_backward_launch_config": (_I, [ctypes.c_int32]),
     "weno_get_backward_launch_config": (None, [ctypes.POINTER(ctypes.c_int32)]),
     "weno_status_string": (ctypes.c_char_p, [_I]),

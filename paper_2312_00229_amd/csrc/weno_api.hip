@@ -46,7 +46,9 @@ __device__ __forceinline__ StripCtx make_ctx(const FwdJob& jb, int n, int c, flo
     return cx;
 }
 
-template <int COLS, int BETA, int IO, bool PACED>
+// TAIL (two columns only): the launch has one-column tail strips
+// (jb.tail_rows > 0) and one wave index across the planes
+template <int COLS, int BETA, int IO, bool PACED, bool TAIL = false>
 __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, int rows_per_strip)
 {
     // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
@@ -60,23 +62,47 @@ __global__ __launch_bounds__(kBlock) void zoom2x_kernel(FwdJob jb, FwdParams P, 
     // of reaching HBM once per plane with a third of their bytes each (1080p
     // RGB uint8: writes 3.0x -> 1.0x the output, reads 4.1x -> 1.1x the
     // input).  Otherwise the XCD of a strip rotates from plane to plane,
-    // which spreads the planes' workgroups evenly over the XCDs.
+    // which spreads the planes' workgroups evenly over the XCDs.  With tail
+    // strips the grid is one-dimensional and every XCD gets a contiguous
+    // range of waves, plane after plane.
     const int nb = gridDim.x, b = blockIdx.x;
     const int xcd = b % kXcds, k = b / kXcds;
     const int logical = xcd * (nb / kXcds) + min(xcd, nb % kXcds) + k;
     // the wave index is the same in every lane; say so, so that strip rows and
     // buffer offsets live in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(logical * kWavesPerBlock + (threadIdx.x >> 6));
-    const int per_plane = jb.strips_x * jb.strips_y;
-    if (wave >= per_plane) return;  // whole wave
-    const int plane = blockIdx.y;
-    const int sy = wave / jb.strips_x;
-    const int sx = wave - sy * jb.strips_x;
-    const int n = plane / jb.C, c = plane - n * jb.C;
-    const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
-    const int R0 = sy * rows_per_strip;
-    const int R1 = min(R0 + rows_per_strip, jb.H);
-    zoom_strip<COLS, BETA, IO, PACED>(cx, P, sx, R0, R1);
+    if constexpr (TAIL) {
+        // One wave index across the planes (gridDim.y is 1).  Per plane: the
+        // two-column strips, band by band, then the one-column strips of the
+        // last columns (no more than a one-column strip owns), whose bands
+        // are taller so that each walks about as long as a two-column strip.
+        static_assert(COLS == 2, "tail strips follow two-column strips");
+        const int n2 = jb.strips_x * jb.strips_y, per_plane = n2 + jb.tail_bands;
+        const int plane = wave / per_plane;
+        if (plane >= jb.planes) return;  // whole wave
+        const int w = wave - plane * per_plane;
+        const int n = plane / jb.C, c = plane - n * jb.C;
+        const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
+        if (w < n2) {
+            const int sy = w / jb.strips_x, sx = w - sy * jb.strips_x;
+            const int R0 = sy * rows_per_strip;
+            zoom_strip<2, BETA, IO, PACED>(cx, P, sx * strip_own<2>(), R0, min(R0 + rows_per_strip, jb.H));
+        } else {
+            const int R0 = (w - n2) * jb.tail_rows;
+            zoom_strip<1, BETA, IO, PACED>(cx, P, jb.strips_x * strip_own<2>(), R0, min(R0 + jb.tail_rows, jb.H));
+        }
+    } else {
+        const int per_plane = jb.strips_x * jb.strips_y;
+        if (wave >= per_plane) return;  // whole wave
+        const int plane = blockIdx.y;
+        const int sy = wave / jb.strips_x;
+        const int sx = wave - sy * jb.strips_x;
+        const int n = plane / jb.C, c = plane - n * jb.C;
+        const StripCtx cx = make_ctx(jb, n, c, P.out_scale);
+        const int R0 = sy * rows_per_strip;
+        const int R1 = min(R0 + rows_per_strip, jb.H);
+        zoom_strip<COLS, BETA, IO, PACED>(cx, P, sx * strip_own<COLS>(), R0, R1);
+    }
 }
 
 // Persistent kernel over a work queue of strips of many images.  Item i of
@@ -123,11 +149,11 @@ __global__ __launch_bounds__(kBlock) void zoom2x_batched_kernel(const BatchTable
         const int R0 = sy * rows_per_strip;
         const int R1 = min(R0 + rows_per_strip, jb.H);
         switch (jb.io) {
-        case kIoF32: zoom_strip<COLS, BETA, kIoF32>(cx, P, sx, R0, R1); break;
-        case kIoU8: zoom_strip<COLS, BETA, kIoU8>(cx, P, sx, R0, R1); break;
-        case kIoU8F32: zoom_strip<COLS, BETA, kIoU8F32>(cx, P, sx, R0, R1); break;
-        case kIoF32U8: zoom_strip<COLS, BETA, kIoF32U8>(cx, P, sx, R0, R1); break;
-        default: zoom_strip<COLS, BETA, kIoGeneric>(cx, P, sx, R0, R1); break;
+        case kIoF32: zoom_strip<COLS, BETA, kIoF32>(cx, P, sx * strip_own<COLS>(), R0, R1); break;
+        case kIoU8: zoom_strip<COLS, BETA, kIoU8>(cx, P, sx * strip_own<COLS>(), R0, R1); break;
+        case kIoU8F32: zoom_strip<COLS, BETA, kIoU8F32>(cx, P, sx * strip_own<COLS>(), R0, R1); break;
+        case kIoF32U8: zoom_strip<COLS, BETA, kIoF32U8>(cx, P, sx * strip_own<COLS>(), R0, R1); break;
+        default: zoom_strip<COLS, BETA, kIoGeneric>(cx, P, sx * strip_own<COLS>(), R0, R1); break;
         }
     }
 }
@@ -299,7 +325,10 @@ int wz_source_region(const weno_tensor_t* src, int boundary, weno_tensor_t* regi
     return WENO_OK;
 }
 
-FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols, int rows_per_strip, int boundary)
+// tail_rows > 0 (two columns only): the last strip column is walked by
+// one-column strips of tail_rows rows (zoom2x_kernel)
+FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols, int rows_per_strip, int boundary,
+                   int tail_rows)
 {
     FwdJob jb;
     const int64_t ei = wz_esize(src->dtype), eo = wz_esize(dst->dtype);
@@ -319,9 +348,16 @@ FwdJob wz_make_job(const weno_tensor_t* src, const weno_tensor_t* dst, int cols,
     jb.d_w = dst->sw * eo;
     jb.in_u8 = src->dtype == WENO_U8;
     jb.out_u8 = dst->dtype == WENO_U8;
-    const int own = cols == 1 ? kWave - 9 : 2 * kWave - 10;
+    const int own = cols == 1 ? strip_own<1>() : strip_own<2>();
     jb.strips_x = (src->w + own - 1) / own;
     jb.strips_y = (src->h + rows_per_strip - 1) / rows_per_strip;
+    jb.tail_rows = 0;
+    jb.tail_bands = 0;
+    if (cols == 2 && tail_rows > 0 && jb.strips_x >= 2 && src->w - (jb.strips_x - 1) * own <= strip_own<1>()) {
+        jb.strips_x -= 1;
+        jb.tail_rows = tail_rows;
+        jb.tail_bands = (src->h + tail_rows - 1) / tail_rows;
+    }
     // vector stores need contiguous rows and aligned plane/row starts
     const uintptr_t base = (uintptr_t)dst->data;
     int vec = 0;
@@ -421,6 +457,18 @@ static hipError_t launch_fwd_beta(const FwdJob& jb, const FwdParams& P, int rows
 {
     const bool share = planes_share_lines(jb.C, jb.s_c, jb.s_h) || planes_share_lines(jb.C, jb.d_c, jb.d_h);
     dim3 grid(fwd_grid_x((int64_t)jb.strips_x * jb.strips_y, share), jb.planes);
+    if constexpr (COLS == 2) {
+        if (jb.tail_rows > 0) {  // one wave index across the planes
+            const int64_t waves = (int64_t)jb.planes * ((int64_t)jb.strips_x * jb.strips_y + jb.tail_bands);
+            grid = dim3((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock), 1);
+            if ((int64_t)grid.x <= (int64_t)fwd_resident_blocks<COLS, BETA, IO>() * device_cus())
+                hipLaunchKernelGGL((zoom2x_kernel<COLS, BETA, IO, true, true>), grid, dim3(kBlock), 0, st, jb, P, rows);
+            else
+                hipLaunchKernelGGL((zoom2x_kernel<COLS, BETA, IO, false, true>), grid, dim3(kBlock), 0, st, jb, P,
+                                   rows);
+            return hipGetLastError();
+        }
+    }
     const int64_t blocks = (int64_t)grid.x * grid.y;
     if (blocks <= (int64_t)fwd_resident_blocks<COLS, BETA, IO>() * device_cus())
         hipLaunchKernelGGL((zoom2x_kernel<COLS, BETA, IO, true>), grid, dim3(kBlock), 0, st, jb, P, rows);
@@ -488,13 +536,22 @@ static double iteration_cost(int cols, int64_t m)
 }
 constexpr int kStartCost = 4;
 
-void wz_auto_config(int64_t planes, int H, int W, bool share, int* rows, int* cols)
+// Tail strips: when the columns left of the last two-column strip fit one
+// one-column strip, that strip column can be walked in one-column strips
+// (half the work per row) with bands kTailStretch / 4 times as tall, so that
+// each walks about as long as a two-column strip (a one-column iteration
+// costs ~0.59 of a two-column one in the fit); the launch then numbers its
+// waves across the planes.  48x512x512: four two-column strips and 40
+// columns per band, 80.1 -> 71.9 predicted.
+constexpr int kTailStretch = 7;
+
+void wz_auto_config(int64_t planes, int H, int W, bool share, int* rows, int* cols, int* tail_rows)
 {
     const int64_t cus = device_cus();
     double best = 0.0;
-    int best_rows = 8, best_cols = 2;
+    int best_rows = 8, best_cols = 2, best_tail = 0;
     for (int c = 2; c >= 1; --c) {
-        const int own = c == 1 ? kWave - 9 : 2 * kWave - 10;
+        const int own = c == 1 ? strip_own<1>() : strip_own<2>();
         const int64_t strips_x = (W + own - 1) / own;
         for (int64_t m = 1; m <= 8; ++m) {
             // the most bands whose workgroups (planes x ceil(strips / 4), padded
@@ -512,29 +569,79 @@ void wz_auto_config(int64_t planes, int H, int W, bool share, int* rows, int* co
                 best = cost;
                 best_rows = r;
                 best_cols = c;
+                best_tail = 0;
+            }
+        }
+    }
+    // two-column strips with a one-column tail strip column (planar only)
+    const int64_t sx = (W + strip_own<2>() - 1) / strip_own<2>();
+    if (!share && sx >= 2 && W - (sx - 1) * strip_own<2>() <= strip_own<1>()) {
+        const int64_t s2 = sx - 1;
+        for (int64_t m = 1; m <= 8; ++m) {
+            // waves per plane: s2 x bands + tail bands (~ bands x 4 / kTailStretch)
+            const int64_t per_plane = kWavesPerBlock * m * cus / planes;
+            int64_t bands = per_plane * kTailStretch / (s2 * kTailStretch + 4);
+            if (bands < 1) bands = 1;
+            int r = (int)((H + bands - 1) / bands);
+            r = r < 4 ? 4 : (r > 4096 ? 4096 : r);
+            int rt = r * kTailStretch / 4;
+            rt = rt > H ? H : rt;
+            const int64_t waves = planes * (s2 * ((H + r - 1) / r) + (H + rt - 1) / rt);
+            const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+            const int64_t mm = (blocks + cus - 1) / cus;
+            const double cost = (double)mm * (r + kStartCost) * iteration_cost(2, mm);
+            if (cost < best) {
+                best = cost;
+                best_rows = r;
+                best_cols = 2;
+                best_tail = rt;
             }
         }
     }
     *rows = best_rows;
     *cols = best_cols;
+    *tail_rows = best_tail;
 }
 
-void wz_config_for(const weno_tensor_t* src, const weno_tensor_t* dst, int* rows, int* cols)
+// launch shape of one doubling: the caller's (weno_set_launch_config, never
+// with tail strips) or the cost model's
+void wz_config_for(const weno_tensor_t* src, const weno_tensor_t* dst, int* rows, int* cols, int* tail_rows)
 {
     *rows = g_rows_per_strip.load();
     *cols = g_cols_per_lane.load();
+    *tail_rows = 0;
     const bool share = planes_share_lines(src->c, src->sc, src->sh) || planes_share_lines(dst->c, dst->sc, dst->sh);
-    if (*rows == 0 || *cols == 0) wz_auto_config((int64_t)src->n * src->c, src->h, src->w, share, rows, cols);
+    if (*rows == 0 || *cols == 0)
+        wz_auto_config((int64_t)src->n * src->c, src->h, src->w, share, rows, cols, tail_rows);
 }
 
 int wz_launch_fwd(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, hipStream_t st,
-                  int rows, int cols)
+                  int rows, int cols, int tail_rows)
 {
-    const FwdJob jb = wz_make_job(src, dst, cols, rows, p->boundary);
+    const FwdJob jb = wz_make_job(src, dst, cols, rows, p->boundary, tail_rows);
     const FwdParams P = wz_fwd_params(p, jb.in_u8, jb.out_u8);
     const int bm = wz_beta_mode(p->beta);
     const hipError_t e = cols == 1 ? launch_fwd_cols<1>(jb, P, bm, rows, st) : launch_fwd_cols<2>(jb, P, bm, rows, st);
     if (e != hipSuccess) return wz_hip_error(e, "zoom2x_kernel launch");
+    return WENO_OK;
+}
+
+extern "C" int weno_query_launch_config(const weno_tensor_t* src, const weno_tensor_t* dst, int32_t* rows_per_strip,
+                                        int32_t* cols_per_lane, int32_t* tail_rows)
+{
+    int rc = wz_check_tensor(src);
+    if (rc) return rc;
+    if (dst) {
+        rc = wz_check_tensor(dst);
+        if (rc) return rc;
+        if (dst->n != src->n || dst->c != src->c || (int64_t)dst->h != 2ll * src->h || (int64_t)dst->w != 2ll * src->w)
+            return WENO_EINVAL;
+    }
+    int rows, cols, tail;
+    wz_config_for(src, dst ? dst : src, &rows, &cols, &tail);
+    if (rows_per_strip) *rows_per_strip = rows;
+    if (cols_per_lane) *cols_per_lane = cols;
+    if (tail_rows) *tail_rows = tail;
     return WENO_OK;
 }
 
@@ -550,9 +657,9 @@ extern "C" int weno_zoom2x(const weno_tensor_t* src, const weno_tensor_t* dst, c
     if (rc) return rc;
     rc = wz_check_region(src, dst, p->boundary);
     if (rc) return rc;
-    int rows, cols;
-    wz_config_for(src, dst, &rows, &cols);
-    return wz_launch_fwd(src, dst, p, (hipStream_t)hip_stream, rows, cols);
+    int rows, cols, tail;
+    wz_config_for(src, dst, &rows, &cols, &tail);
+    return wz_launch_fwd(src, dst, p, (hipStream_t)hip_stream, rows, cols, tail);
 }
 
 // --------------------------------------------------------------------------
@@ -630,7 +737,7 @@ extern "C" int weno_zoom2x_batched_plan(const weno_tensor_t* srcs, const weno_te
     int64_t total = 0;
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
-        jobs[k] = wz_make_job(&srcs[i], &dsts[i], cols, rows, p->boundary);
+        jobs[k] = wz_make_job(&srcs[i], &dsts[i], cols, rows, p->boundary, 0);
         prm[k] = wz_fwd_params(p, jobs[k].in_u8, jobs[k].out_u8);
         prefix[k] = total;
         total += (int64_t)jobs[k].planes * jobs[k].strips_x * jobs[k].strips_y;
@@ -831,8 +938,9 @@ extern "C" int weno_zoom2x_cascade(const weno_tensor_t* src, const weno_tensor_t
         lp.h = (float)(p->h * scale);
         lp.nbw = (float)(w0 * scale * scale);
         int rows, cols;
-        wz_config_for(&cur, &out, &rows, &cols);
-        rc = wz_launch_fwd(&cur, &out, &lp, (hipStream_t)hip_stream, rows, cols);
+        int tail;
+        wz_config_for(&cur, &out, &rows, &cols, &tail);
+        rc = wz_launch_fwd(&cur, &out, &lp, (hipStream_t)hip_stream, rows, cols, tail);
         if (rc) return rc;
         cur = out;
     }

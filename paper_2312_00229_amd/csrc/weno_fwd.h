@@ -85,7 +85,11 @@ struct FwdJob {
     int64_t s_n, s_c, s_h, s_w;       // byte strides of the source
     int64_t d_n, d_c, d_h, d_w;       // byte strides of the destination
     int32_t in_u8, out_u8;            // element types
-    int32_t strips_x, strips_y;       // strips per plane
+    int32_t strips_x, strips_y;       // strips per plane (two-column strips only when tail_rows > 0)
+    // tail_rows > 0: the columns left of the last two-column strip are
+    // walked by one-column strips of tail_rows rows, tail_bands of them per
+    // plane (single-image planar launches; zoom2x_kernel)
+    int32_t tail_rows, tail_bands;
     int32_t vec;                      // 2: float4 rows, 1: float2 rows, 0: scalar stores
     uint32_t src_extent, dst_extent;  // bytes spanned by one plane (< 2^31)
     int32_t io;                       // I/O mode (kIo*)
@@ -588,19 +592,24 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
     }
 }
 
-// Walk one strip: columns [Jbase, Jbase + 64*COLS), output rows [R0, R1).
+// Input columns a strip of COLS quad columns per lane owns (stores): the
+// 64*COLS it walks less a halo of 4 on the left and 5 or 6 on the right (a
+// quad reads columns J-4 .. J+5); even for COLS = 2 (16-byte stores).
+template <int COLS>
+constexpr int strip_own() { return COLS == 1 ? kWave - 9 : 2 * kWave - 10; }
+
+// Walk one strip: owned columns [c0, c0 + strip_own), output rows [R0, R1).
 // PACED: the launch runs as one round of waves (every wave resident from the
 // start): pace the waves that share a SIMD and write whole output rows
 // through the L2.
 template <int COLS, int BETA, int IO, bool PACED = false>
-__device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& P, int strip_x, int R0, int R1)
+__device__ __forceinline__ void zoom_strip(const StripCtx& cx, const FwdParams& P, int c0, int R0, int R1)
 {
     constexpr int ST = PACED ? kStRows : 0;
-    constexpr int SPAN = kWave * COLS;
     constexpr int HALO_L = 4;
-    constexpr int OWN = (COLS == 1) ? SPAN - 9 : SPAN - 10;  // even for COLS = 2 (16-byte stores)
+    constexpr int OWN = strip_own<COLS>();
     const int lane = threadIdx.x & (kWave - 1);
-    const int Jbase = strip_x * OWN - HALO_L;
+    const int Jbase = c0 - HALO_L;
     StripLanes<COLS> L;
     L.own_all = true;
 #pragma unroll

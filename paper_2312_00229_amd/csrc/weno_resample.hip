@@ -761,8 +761,8 @@ extern "C" size_t weno_zoom_to_workspace(const weno_tensor_t* src, const weno_te
 }
 
 int wz_launch_fwd(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p, hipStream_t st, int rows,
-                  int cols);
-void wz_config_for(const weno_tensor_t* src, const weno_tensor_t* dst, int* rows, int* cols);
+                  int cols, int tail_rows);
+void wz_config_for(const weno_tensor_t* src, const weno_tensor_t* dst, int* rows, int* cols, int* tail_rows);
 
 extern "C" int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, const weno_params_t* p,
                             void* d_workspace, size_t ws_bytes, void* hip_stream)
@@ -791,8 +791,9 @@ extern "C" int weno_zoom_to(const weno_tensor_t* src, const weno_tensor_t* dst, 
         lp.h = (float)(p->h * scale);
         lp.nbw = (float)(w0 * scale * scale);
         int rows, cols;
-        wz_config_for(&cur, &out, &rows, &cols);
-        rc = wz_launch_fwd(&cur, &out, &lp, st, rows, cols);
+        int tail;
+        wz_config_for(&cur, &out, &rows, &cols, &tail);
+        rc = wz_launch_fwd(&cur, &out, &lp, st, rows, cols, tail);
         if (rc) return rc;
         // the paper's nested grid: the leading (2n - 1) x (2m - 1) samples
         cur = out;

@@ -204,6 +204,39 @@ def test_launch_config_validation():
     assert L.weno_set_backward_launch_config(0) == _lib.WENO_OK
 
 
+def _query(src, dst):
+    r, c, t = ctypes.c_int32(-1), ctypes.c_int32(-1), ctypes.c_int32(-1)
+    rc = _lib.lib().weno_query_launch_config(ctypes.byref(src) if src is not None else None,
+                                             ctypes.byref(dst) if dst is not None else None,
+                                             ctypes.byref(r), ctypes.byref(c), ctypes.byref(t))
+    return rc, (r.value, c.value, t.value)
+
+
+def test_query_launch_config():
+    L = _lib.lib()
+    assert _query(None, None)[0] == _lib.WENO_EINVAL
+    assert _query(_t(ptr=0), None)[0] == _lib.WENO_EINVAL
+    assert _query(_t(), _t(ptr=0x100000, h=8, w=9))[0] == _lib.WENO_EINVAL          # not 2x
+    assert L.weno_query_launch_config(ctypes.byref(_t()), None, None, None, None) == _lib.WENO_OK
+    # the caller's configuration, never with tail strips
+    assert L.weno_set_launch_config(64, 2) == _lib.WENO_OK
+    try:
+        assert _query(_t(n=16, c=3, h=512, w=512), None) == (_lib.WENO_OK, (64, 2, 0))
+    finally:
+        assert L.weno_set_launch_config(0, 0) == _lib.WENO_OK
+    # the automatic choice (a 256-CU device, also where no device is visible)
+    rc, (r, c, t) = _query(_t(c=3, h=1080, w=1920), None)
+    assert rc == _lib.WENO_OK and (r, c, t) == (27, 2, 0)
+    # 512 wide: four two-column strips and 40 columns, walked as a tail column
+    rc, (r, c, t) = _query(_t(n=16, c=3, h=512, w=512), None)
+    assert rc == _lib.WENO_OK and c == 2 and t > r
+    # interleaved (HWC) planes never take tail strips
+    hwc = WenoTensor(0x1000, _lib.WENO_U8, 16, 3, 512, 512, 3 * 512 * 512, 1, 3 * 512, 3)
+    hwc_out = WenoTensor(0x10000000, _lib.WENO_U8, 16, 3, 1024, 1024, 3 * 1024 * 1024, 1, 3 * 1024, 3)
+    rc, (r, c, t) = _query(hwc, hwc_out)
+    assert rc == _lib.WENO_OK and t == 0
+
+
 def test_status_strings():
     for s in (0, -1, -2, -3, -4, -5, -99):
         assert isinstance(_lib.status_string(s), str)

@@ -213,6 +213,44 @@ def test_paced_and_unpaced_launches_bit_identical(gpu, dtype):
         check_u8(got, ref, "paced/unpaced u8 band")
 
 
+@pytest.mark.parametrize("shape", [(3, 512, 512), (48, 512, 512), (3, 480, 640), (1, 2048, 2048), (3, 96, 173)])
+@pytest.mark.parametrize("dtypes", ["f32->f32", "u8->u8", "u8->f32", "f32->u8"])
+def test_tail_strips(gpu, shape, dtypes):
+    # Planar images whose last strip column holds no more than a one-column
+    # strip owns: the automatic launch walks it in one-column strips of
+    # taller bands and numbers its waves across the planes.  Must match a
+    # launch without tail strips bit for bit, and the oracle.
+    _set(gpu, (0, 0))
+    rng = np.random.default_rng(shape[1] * 7 + shape[2])
+    img = (rng.random(shape) * 0.6 + np.linspace(0, 0.4, shape[2])[None, None, :]).astype(np.float32)
+    src_u8 = dtypes.startswith("u8")
+    x = torch.tensor(np.rint(img * 255).astype(np.uint8) if src_u8 else img, device="cuda")
+    out_dtype = torch.uint8 if dtypes.endswith("u8") else torch.float32
+    rows, cols, tail = gpu.launch_shape(x)
+    if shape != (3, 96, 173):
+        assert cols == 2 and tail > 0, (rows, cols, tail)
+    y = gpu.zoom2x(x, out_dtype=out_dtype)
+    _set(gpu, (rows, 2))
+    assert gpu.launch_shape(x) == (rows, 2, 0)
+    y2 = gpu.zoom2x(x, out_dtype=out_dtype)
+    _set(gpu, (0, 0))
+    a, b = y.cpu().numpy(), y2.cpu().numpy()
+    assert np.array_equal(a, b), shape
+    V = (x.cpu().numpy().astype(np.float64) / 255.0) if src_u8 else img.astype(np.float64)
+    if shape[0] * shape[1] * shape[2] <= 3 * 512 * 512:
+        ref = oracle.zoom2x(V)
+    else:   # the last planes, on a window over the tail columns and the band boundaries
+        V = V[-2:]
+        a = a[-2:]
+        c0 = shape[2] - 150
+        ref = oracle.window_zoom2x(V, 0, 160, c0, shape[2])
+        a = a[:, :320, 2 * c0:]
+    if dtypes.endswith("u8"):
+        check_u8(a, ref, "tail strips %s %s" % (shape, dtypes))
+    else:
+        assert np.abs(a - ref).max() <= TOL
+
+
 def test_interleaved_and_planar_layouts_bit_identical(gpu):
     # HWC images launch on a grid padded to a multiple of the XCD count (the
     # same strip of every channel on one XCD) and take their own strip height
