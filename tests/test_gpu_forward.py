@@ -354,6 +354,24 @@ def test_external_boundary_f32(gpu, shape):
     assert np.array_equal(U, full)
 
 
+def test_external_boundary_with_tail_strips(gpu):
+    # three 512x512 planes viewed inside larger ones (ghost samples read in
+    # place), launched with one-column tail strips for the last 40 columns
+    _set(gpu, (0, 0))
+    H = W = 512
+    E = np.stack([random_plane(H + 12, W + 15, seed=70 + k, kind="steps") for k in range(3)]).astype(np.float32)
+    r0, c0 = 5, 7
+    Et = _f32(E)
+    view = Et[:, r0:r0 + H, c0:c0 + W]
+    assert gpu.launch_shape(view)[2] > 0
+    U = gpu.zoom2x(view, boundary="external").cpu().numpy()
+    region = E[:, r0 - 4:r0 + H + 5, c0 - 4:c0 + W + 5]
+    full = gpu.zoom2x(_f32(region)).cpu().numpy()[:, 8:8 + 2 * H, 8:8 + 2 * W]
+    assert np.array_equal(U, full)
+    ref = oracle.window_zoom2x(region[1].astype(np.float64), 4, 60, W + 4 - 60, W + 4)
+    assert np.abs(U[1, :112, 2 * (W - 60):] - ref).max() <= TOL
+
+
 def test_external_boundary_u8_hwc_and_batched(gpu):
     _set(gpu, (0, 0))
     img = scene_rgb(70, 130, seed=4, n_polygons=6)
