@@ -1,7 +1,9 @@
 """Seeded random cases across the parameter space, each against the FP64
 oracle: sizes from 1 to 300, batches of one or two, one or three channels,
 planar or channel-interleaved layouts, float32 or uint8 at either end, beta
-in {1, 1.5, 2}, automatic or forced launch shapes; the adjoint on float32;
+in {1, 1.5, 2}, automatic or forced launch shapes (and automatic shapes over
+many planes and widths, one-column tail strips among them, against a forced
+one); the adjoint on float32;
 the resampler up and down.  The bars are those of the targeted tests:
 float32 within 1e-5 of max(1, |ref|), uint8 codes equal up to counted
 rounding ties, the adjoint within the bar of conftest.check_adjoint."""
@@ -66,6 +68,45 @@ def test_random_forward(gpu, seed):
         check_u8(got, ref, str(what), max_tie_frac=5e-5)
     else:
         assert np.abs(got - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max()), what
+
+
+def _has_tail(w):
+    """The width leaves a last strip column one one-column strip can hold."""
+    own2, own1 = 118, 55
+    sx = -(-w // own2)
+    return sx >= 2 and w - (sx - 1) * own2 <= own1
+
+
+@pytest.mark.parametrize("seed", range(300, 330))
+def test_random_automatic_launch_shapes(gpu, seed):
+    # Automatic launch shapes over many planes and widths (one-dimensional
+    # grids with one-column tail strips among them) against a forced shape
+    # without tail strips, bit for bit, and the oracle on the last plane's
+    # tail columns.
+    rng = np.random.default_rng(seed)
+    planes = int(rng.integers(1, 49))
+    h = int(rng.integers(4, 400))
+    tails = [w for w in range(120, 1200) if _has_tail(w)]
+    w = int(rng.choice(tails)) if rng.random() < 0.8 else int(rng.integers(4, 1200))
+    u8 = rng.random() < 0.3
+    a = rng.random((planes, h, w))
+    x = torch.tensor((a * 255).round().astype(np.uint8) if u8 else a.astype(np.float32), device="cuda")
+    gpu.set_launch_config(0, 0)
+    rows, cols, tail = gpu.launch_shape(x)
+    y = gpu.zoom2x(x).cpu().numpy()
+    gpu.set_launch_config(16, 1)
+    y2 = gpu.zoom2x(x).cpu().numpy()
+    gpu.set_launch_config(0, 0)
+    print("seed %d: %d x %d x %d %s, shape %s" % (seed, planes, h, w, "u8" if u8 else "f32", (rows, cols, tail)))
+    assert np.array_equal(y, y2)
+    V = (x[-1].cpu().numpy().astype(np.float64) / 255.0) if u8 else x[-1].cpu().numpy().astype(np.float64)
+    c0 = max(0, w - 70)
+    ref = oracle.window_zoom2x(V, 0, min(h, 40), c0, w)
+    got = y[-1, :2 * min(h, 40), 2 * c0:]
+    if u8:
+        check_u8(got, ref, "seed %d" % seed)
+    else:
+        assert np.abs(got - ref).max() <= 1e-5
 
 
 @pytest.mark.parametrize("seed", range(100, 112))
