@@ -473,7 +473,9 @@ __device__ __forceinline__ void strip_step(StripState<COLS>& s, raw_t<IO> (&Q)[C
             float t[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                float ns = (s.SX1[k][c] + SX3[k][c]) + (lft(s.SX2[k], c) + rgt(s.SX2[k], c));
+                // one neighbour shift per addition, so that with one column per
+                // lane each shift folds into its addition as a DPP operand
+                float ns = ((s.SX1[k][c] + SX3[k][c]) + lft(s.SX2[k], c)) + rgt(s.SX2[k], c);
                 t[k] = __builtin_fmaf(w, ns, s.SX2[k][c]);
             }
             X2[c] = blend4<BETA>(t[0], t[1], t[2], t[3], s.PX2[0][c], s.PX2[1][c], s.PX2[2][c], s.PX2[3][c], P.beta);
