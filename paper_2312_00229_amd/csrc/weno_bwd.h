@@ -236,9 +236,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // rows outside it read through an offset past the end of the buffer, which
     // the buffer unit answers with 0 and no memory access, so the loads need no
     // branch and can be issued a step before their use
-    constexpr uint32_t kOob = 0x80000000u;   // above every plane extent (< 2^31)
-    const uint32_t gyoffA = colin ? (uint32_t)(2 * jc) * cx.gy_w : kOob;        // column 2J
-    const uint32_t gyoffB = colin ? (uint32_t)(2 * jc + 1) * cx.gy_w : kOob;    // column 2J+1
+    // Lanes outside the image read at column offset kOobCol, rows outside it
+    // at row offset kOobRow: either puts the sum at or above every plane
+    // extent (< 2^31), and the two together stay below 2^32 (no wrap).  The
+    // row offset is uniform, so the choice for a row is a scalar select.
+    constexpr uint32_t kOobCol = 0x7fffffffu, kOobRow = 0x80000000u;
+    const uint32_t gyoffA = colin ? (uint32_t)(2 * jc) * cx.gy_w : kOobCol;        // column 2J
+    const uint32_t gyoffB = colin ? (uint32_t)(2 * jc + 1) * cx.gy_w : kOobCol;    // column 2J+1
     const uint32_t gxoff = (uint32_t)jc * cx.gx_w;
     const bool first_strip = c0 == 0;
     const bool last_strip = c0 + width >= W;
@@ -251,7 +255,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     };
     auto ldG = [&](int r, uint32_t off) {   // dL/dU element, 0 outside the 2H x 2W grid
         const bool in = r >= 0 && r < 2 * H;
-        return buf_ld_f32(cx.gy, in ? off : kOob, in ? (uint32_t)r * cx.gy_h : 0u);
+        return buf_ld_f32(cx.gy, off, in ? (uint32_t)r * cx.gy_h : kOobRow);
     };
     auto stG = [&](int r, float val) { buf_st_f32(val, cx.gx, gxoff, (uint32_t)r * cx.gx_h); };
 
