@@ -293,7 +293,7 @@ FwdParams wz_fwd_params(const weno_params_t* p, int in_u8, int out_u8)
     FwdParams P;
     // with beta = 0 the weights are t^0 = 1 whatever the indicator, and eps
     // (which may then be 0) only has to keep t away from 0 for log2
-    P.eps_hat = p->beta == 0.0f ? 1.0f : (float)(eps * (12.0 / 13.0) / (1.0 + 4.0 * w));
+    P.eps_hat = p->beta == 0.0f ? 1.0f : (float)(eps * (3.0 / 13.0) / (1.0 + 4.0 * w));
     P.eps_q = p->beta == 0.0f ? 1.0f : (float)(eps / (4.0 * (1.0 + 4.0 * w)));
     P.w = (float)w;
     P.beta = p->beta;

@@ -9,10 +9,14 @@
 // t_k takes its own indicator with weight 1 and four neighbour indicators of
 // the same direction with weight w; a candidate and an indicator of a stencil
 // (a, b, c) (nodes -1, 1, 3; g = b - a, dd = a - 2b + c) have
-//     p  = (a + b)/2 - dd/8            dp/d(a,b,c)  = (3/8, 3/4, -1/8)
-//     SI' = (12/13) g^2 + dd^2          dSI'/d(a,b,c) = (-(24/13)g + 2dd, (24/13)g - 4dd, 2dd)
-// (the kernels carry SI' = (12/13) SI; t' = (12/13) t and the formula for
-// du/dt'_k is the same in the scaled variables).
+//     p = (a + b)/2 - dd/8,     dp/d(a,b,c) = (3/8, 3/4, -1/8).
+// The walk keeps half samples (v/2 of the input and of the x points), so a
+// stencil gives gh = g/2, ddh = dd/2 and the midpoint (a + b)/2 = ha + hb in
+// one addition, and it carries the indicators scaled by 3/13:
+//     SI* = (3/13) SI = gh f + ddh^2 with f = (12/13) gh,
+//     dSI*/d(a,b,c) = (ddh - f, f - 2 ddh, ddh),
+// so each derivative term is one product (t* = (3/13) t, and the formula
+// for du/dt*_k is the same in the scaled variables).
 //
 // Work decomposition: like the forward, one wave walks a strip of 64 input
 // columns (one per lane) down the image; horizontal neighbours come from DPP
@@ -183,26 +187,30 @@ __device__ __forceinline__ float blend_seed(const float (&t)[4], const float (&p
     return u;
 }
 
+// slope factor of an indicator in the scale 3/13: f = (12/13) gh
+constexpr float kSlopeF = 12.0f / 13.0f;
+__device__ __forceinline__ float slope_f(float gh) { return kSlopeF * gh; }
+// candidate (a + b)/2 - dd/8 from the midpoint m = ha + hb and ddh = dd/2
+__device__ __forceinline__ float cand_h(float ddh, float m) { return __builtin_fmaf(ddh, -0.25f, m); }
+
 // adjoint of the two stencils of one line: the forward one (x0, x1, x2) and
-// the backward one (x1, x0, x-1), with g = x1 - x0 (the forward stencil's;
-// the backward one's is -g) and their own second differences ddf, ddb.
-// Returns the gradients at x0 (s0 = ga_f + gb_b), x1 (s1 = gb_f + ga_b), x2
-// (cf) and x-1 (cb).  A stencil (a, b, c) with candidate seed gp and
-// indicator seed gs gives
-//   ga = 3/8 gp + gs (2 dd - (24/13) g),  gb = 3/4 gp + gs ((24/13) g - 4 dd),
-//   gc = -1/8 gp + 2 gs dd;
+// the backward one (x1, x0, x-1), with slope factor f = (12/13)(x1 - x0)/2
+// (the forward stencil's; the backward one's is -f) and their own half second
+// differences ddf, ddb.  Returns the gradients at x0 (s0 = ga_f + gb_b), x1
+// (s1 = gb_f + ga_b), x2 (cf) and x-1 (cb).  A stencil (a, b, c) with
+// candidate seed gp and seed gs of its scaled indicator gives
+//   ga = 3/8 gp + gs (ddh - f),  gb = 3/4 gp + gs (f - 2 ddh),  gc = -1/8 gp + gs ddh;
 // written per line rather than per stencil, the slope terms of the two
-// stencils fold into one product F = (24/13) g (gs_f + gs_b), and with
-// E = 2 gs dd
+// stencils fold into one product F = f (gs_f + gs_b), and with E = gs ddh
 //   s0 = 3/8 gp_f + 3/4 gp_b + E_f - 2 E_b - F
 //   s1 = 3/4 gp_f + 3/8 gp_b - 2 E_f + E_b + F
 //   cf = -1/8 gp_f + E_f,   cb = -1/8 gp_b + E_b
-// (15 operations against 20 for two stencils and the two sums).
-__device__ __forceinline__ void line_adj(float gpf, float gsf, float ddf, float gpb, float gsb, float ddb, float g,
+// (14 operations against 20 for two stencils and the two sums).
+__device__ __forceinline__ void line_adj(float gpf, float gsf, float ddf, float gpb, float gsb, float ddb, float f,
                                          float& s0, float& s1, float& cf, float& cb)
 {
-    const float ef = 2.0f * (gsf * ddf), eb = 2.0f * (gsb * ddb);
-    const float F = (gsf + gsb) * (g * (24.0f / 13.0f));
+    const float ef = gsf * ddf, eb = gsb * ddb;
+    const float F = (gsf + gsb) * f;
     s0 = __builtin_fmaf(gpf, 0.375f, __builtin_fmaf(gpb, 0.75f, __builtin_fmaf(eb, -2.0f, ef - F)));
     s1 = __builtin_fmaf(gpf, 0.75f, __builtin_fmaf(gpb, 0.375f, __builtin_fmaf(ef, -2.0f, eb + F)));
     cf = __builtin_fmaf(gpf, -0.125f, ef);
@@ -260,6 +268,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     auto stG = [&](int r, float val) { buf_st_f32(val, cx.gx, gxoff, (uint32_t)r * cx.gx_h); };
 
     // ---------------- forward state (rows relative to s) ----------------
+    // half samples: V(r) holds v(r)/2, X(r) the x point of row r over 2
     float Vm3 = 0, Vm2 = 0, Vm1 = 0;                    // V(s-3) .. V(s-1)
     float V0 = 0, V1 = 0, V2 = 0, V3 = 0, V4 = 0;       // V(s) .. V(s+4)
     float dd1_3 = 0, dd2s_3 = 0;
@@ -267,9 +276,10 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     float SX1[4] = {1, 1, 1, 1}, SX2[4] = {1, 1, 1, 1}, PX2[4] = {};
     float X0 = 0, X1 = 0, ddXv0 = 0, ddr0 = 0;
     float SB0[4] = {1, 1, 1, 1}, PB0[4] = {}, hB0[4] = {1, 1, 1, 1}, hAm1[4] = {1, 1, 1, 1};
-    // stencil geometry (g, dd per direction) of B(s) and A(s-1)
-    float geoB_gv = 0, geoB_ddd = 0, geoB_ddu = 0, geoB_gh = 0, geoB_ddr = 0, geoB_ddl = 0;
-    float geoA_gv = 0, geoA_ddd = 0, geoA_ddu = 0, geoA_gh = 0, geoA_ddr = 0, geoA_ddl = 0;
+    // stencil geometry (slope factor f, half second differences per
+    // direction) of B(s) and A(s-1)
+    float geoB_fv = 0, geoB_ddd = 0, geoB_ddu = 0, geoB_fh = 0, geoB_ddr = 0, geoB_ddl = 0;
+    float geoA_fv = 0, geoA_ddd = 0, geoA_ddu = 0, geoA_fh = 0, geoA_ddr = 0, geoA_ddl = 0;
     // The seed factors of x row s+2 (omega_k and omega_k (p_k - u) / t_k),
     // made at step s, are used at step s+4.  They wait in LDS rather than in
     // registers: slot s & 3 holds them from step s until step s+4 reads it
@@ -320,7 +330,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         constexpr bool do_dd = FULL || D >= -7, do_sx = FULL || D >= -6, do_x = FULL || D >= -4;
         constexpr bool do_p2dd = FULL || D >= -2, do_p2 = FULL || D >= -1;
         constexpr bool P1 = decltype(p1)::value;
-        const float V5 = Q0;
+        const float V5 = 0.5f * Q0;
         Q0 = Q1;
         Q1 = ldV(s + 7);
         float gA = 0, gB = 0, gXu = 0, gVu = 0;
@@ -355,12 +365,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         float SX3[4] = {1, 1, 1, 1}, PX3[4] = {};
         if constexpr (do_sx) {
             const float a1 = V3, b1 = nbR(V4), a2 = nbR(V3), b2 = V4;
-            const float gc1 = gterm(b1 - a1, eh), gc2 = gterm(b2 - a2, eh);
-            const float m1 = 0.5f * (a1 + b1), m2 = 0.5f * (a2 + b2);
-            SX3[0] = sidx(dd1s_4, gc1);  PX3[0] = cand(dd1s_4, m1);
-            SX3[2] = sidx(dd1_3, gc1);   PX3[2] = cand(dd1_3, m1);
-            SX3[1] = sidx(dd2s_3, gc2);  PX3[1] = cand(dd2s_3, m2);
-            SX3[3] = sidx(dd2_4, gc2);   PX3[3] = cand(dd2_4, m2);
+            const float g1 = b1 - a1, g2 = b2 - a2;
+            const float gc1 = __builtin_fmaf(g1, slope_f(g1), eh), gc2 = __builtin_fmaf(g2, slope_f(g2), eh);
+            const float m1 = a1 + b1, m2 = a2 + b2;
+            SX3[0] = sidx(dd1s_4, gc1);  PX3[0] = cand_h(dd1s_4, m1);
+            SX3[2] = sidx(dd1_3, gc1);   PX3[2] = cand_h(dd1_3, m1);
+            SX3[1] = sidx(dd2s_3, gc2);  PX3[1] = cand_h(dd2s_3, m2);
+            SX3[3] = sidx(dd2_4, gc2);   PX3[3] = cand_h(dd2_4, m2);
         }
         // x row s+2 with its seed factors
         float X2 = 0.0f;
@@ -373,7 +384,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
                 const float ns = ((SX1[k] + SX3[k]) + nbL(SX2[k])) + nbR(SX2[k]);
                 t[k] = __builtin_fmaf(w, ns, SX2[k]);
             }
-            X2 = blend_seed<BETA>(t, PX2, beta, omX2, dkX2);
+            X2 = 0.5f * blend_seed<BETA>(t, PX2, beta, omX2, dkX2);
             // The factors written at iteration s feed the phase-1 seeds of x
             // row s+2 at iteration s+4, which a kept row needs only from the
             // first full iteration's write on (rows s+2 >= R0-3, or >= -7 for
@@ -393,31 +404,33 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         // + points: B(s+1) and A(s)
         float SB1[4] = {1, 1, 1, 1}, PB1[4] = {}, hB1[4] = {1, 1, 1, 1};
         float SA0[4] = {1, 1, 1, 1}, PA0[4] = {}, hA0[4] = {1, 1, 1, 1};
-        float nB_gv = 0, nB_ddd = 0, nB_ddu = 0, nB_gh = 0, nB_ddr = 0, nB_ddl = 0;   // geometry of B(s+1)
-        float nA_gv = 0, nA_ddd = 0, nA_ddu = 0, nA_gh = 0, nA_ddr = 0, nA_ddl = 0;   // geometry of A(s)
+        float nB_fv = 0, nB_ddd = 0, nB_ddu = 0, nB_fh = 0, nB_ddr = 0, nB_ddl = 0;   // geometry of B(s+1)
+        float nA_fv = 0, nA_ddd = 0, nA_ddu = 0, nA_fh = 0, nA_ddr = 0, nA_ddl = 0;   // geometry of A(s)
         if constexpr (do_p2) {
             const float v1r = nbR(V1);
             const float ddc = d2(nbL(V1), V1, v1r);
             const float x0l = nbL(X0);
             const float ddXh = d2(x0l, X0, nbR(X0));
             // B(s+1)
-            nB_gv = X1 - X0;  nB_ddd = ddXv1;  nB_ddu = ddXv0;
-            nB_gh = v1r - V1; nB_ddr = nbR(ddc); nB_ddl = ddc;
-            const float gcv = gterm(nB_gv, eh), mv = 0.5f * (X0 + X1);
-            const float gch = gterm(nB_gh, eh), mh = 0.5f * (V1 + v1r);
-            SB1[0] = sidx(nB_ddd, gcv); PB1[0] = cand(nB_ddd, mv);
-            SB1[2] = sidx(nB_ddu, gcv); PB1[2] = cand(nB_ddu, mv);
-            SB1[1] = sidx(nB_ddr, gch); PB1[1] = cand(nB_ddr, mh);
-            SB1[3] = sidx(nB_ddl, gch); PB1[3] = cand(nB_ddl, mh);
+            const float gBv = X1 - X0, gBh = v1r - V1;
+            nB_fv = slope_f(gBv); nB_ddd = ddXv1;  nB_ddu = ddXv0;
+            nB_fh = slope_f(gBh); nB_ddr = nbR(ddc); nB_ddl = ddc;
+            const float gcv = __builtin_fmaf(gBv, nB_fv, eh), mv = X0 + X1;
+            const float gch = __builtin_fmaf(gBh, nB_fh, eh), mh = V1 + v1r;
+            SB1[0] = sidx(nB_ddd, gcv); PB1[0] = cand_h(nB_ddd, mv);
+            SB1[2] = sidx(nB_ddu, gcv); PB1[2] = cand_h(nB_ddu, mv);
+            SB1[1] = sidx(nB_ddr, gch); PB1[1] = cand_h(nB_ddr, mh);
+            SB1[3] = sidx(nB_ddl, gch); PB1[3] = cand_h(nB_ddl, mh);
             // A(s)
-            nA_gv = V1 - V0;  nA_ddd = ddr1;  nA_ddu = ddr0;
-            nA_gh = X0 - x0l; nA_ddr = ddXh;  nA_ddl = nbL(ddXh);
-            const float gav = gterm(nA_gv, eh), mav = 0.5f * (V0 + V1);
-            const float gah = gterm(nA_gh, eh), mah = 0.5f * (x0l + X0);
-            SA0[0] = sidx(nA_ddd, gav); PA0[0] = cand(nA_ddd, mav);
-            SA0[2] = sidx(nA_ddu, gav); PA0[2] = cand(nA_ddu, mav);
-            SA0[1] = sidx(nA_ddr, gah); PA0[1] = cand(nA_ddr, mah);
-            SA0[3] = sidx(nA_ddl, gah); PA0[3] = cand(nA_ddl, mah);
+            const float gAv = V1 - V0, gAh = X0 - x0l;
+            nA_fv = slope_f(gAv); nA_ddd = ddr1;  nA_ddu = ddr0;
+            nA_fh = slope_f(gAh); nA_ddr = ddXh;  nA_ddl = nbL(ddXh);
+            const float gav = __builtin_fmaf(gAv, nA_fv, eh), mav = V0 + V1;
+            const float gah = __builtin_fmaf(gAh, nA_fh, eh), mah = x0l + X0;
+            SA0[0] = sidx(nA_ddd, gav); PA0[0] = cand_h(nA_ddd, mav);
+            SA0[2] = sidx(nA_ddu, gav); PA0[2] = cand_h(nA_ddu, mav);
+            SA0[1] = sidx(nA_ddr, gah); PA0[1] = cand_h(nA_ddr, mah);
+            SA0[3] = sidx(nA_ddl, gah); PA0[3] = cand_h(nA_ddl, mah);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 hB1[k] = nbL(SB1[k]) + SB1[k];
@@ -466,13 +479,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             for (int k = 0; k < 4; ++k) gs[k] = __builtin_fmaf(w, qB_m1[k] + qB[k], gtA_m1[k]);
             float s0, s1, cf, cb;
             // vertical stencils on V column J: k0 (V(s-1), V(s), V(s+1)), k2 (V(s), V(s-1), V(s-2))
-            line_adj(gpA_m1[0], gs[0], geoA_ddd, gpA_m1[2], gs[2], geoA_ddu, geoA_gv, s0, s1, cf, cb);
+            line_adj(gpA_m1[0], gs[0], geoA_ddd, gpA_m1[2], gs[2], geoA_ddu, geoA_fv, s0, s1, cf, cb);
             accV_m1 += s0;
             accV_0 += s1;
             accV_p1 += cf;
             accV_m2 += cb;
             // horizontal stencils on x row s-1: k1 (x[J-1], x[J], x[J+1]), k3 (x[J], x[J-1], x[J-2])
-            line_adj(gpA_m1[1], gs[1], geoA_ddr, gpA_m1[3], gs[3], geoA_ddl, geoA_gh, s0, s1, cf, cb);
+            line_adj(gpA_m1[1], gs[1], geoA_ddr, gpA_m1[3], gs[3], geoA_ddl, geoA_fh, s0, s1, cf, cb);
             const float u = s0 + nbR(cb);
             accX_m1 += (s1 + nbR(u)) + nbL(cf);
         }
@@ -483,13 +496,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             for (int k = 0; k < 4; ++k) gs[k] = __builtin_fmaf(w, qA_m1[k] + qA[k], gtB[k]);
             float s0, s1, cf, cb;
             // vertical stencils on x column J: k0 (x(s-1), x(s), x(s+1)), k2 (x(s), x(s-1), x(s-2))
-            line_adj(gpB[0], gs[0], geoB_ddd, gpB[2], gs[2], geoB_ddu, geoB_gv, s0, s1, cf, cb);
+            line_adj(gpB[0], gs[0], geoB_ddd, gpB[2], gs[2], geoB_ddu, geoB_fv, s0, s1, cf, cb);
             accX_m1 += s0;
             accX_0 += s1;
             accX_p1 += cf;
             accX_m2 += cb;
             // horizontal stencils on V row s: k1 (V[J], V[J+1], V[J+2]), k3 (V[J+1], V[J], V[J-1])
-            line_adj(gpB[1], gs[1], geoB_ddr, gpB[3], gs[3], geoB_ddl, geoB_gh, s0, s1, cf, cb);
+            line_adj(gpB[1], gs[1], geoB_ddr, gpB[3], gs[3], geoB_ddl, geoB_fh, s0, s1, cf, cb);
             const float v = s1 + nbL(cf);
             accV_0 += (s0 + nbL(v)) + nbR(cb);
         }
@@ -506,8 +519,9 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         if constexpr (P1) {
             const float Qv = Vm3, Rv = Vm2;
             const float dd1_r = ddm3.x, dd2s_r = ddm3.y, dd1s_r1 = ddm2.x, dd2_r1 = ddm2.y;
-            const float g1 = nbR(Rv) - Qv;         // V(r+1)[J+1] - V(r)[J]
-            const float g2 = Rv - nbR(Qv);         // V(r+1)[J] - V(r)[J+1]
+            // slope factors of the forward stencils k0 and k1
+            const float f1 = slope_f(nbR(Rv) - Qv);   // from V(r+1)[J+1] - V(r)[J]
+            const float f2 = slope_f(nbR(Qv) - Rv);   // from V(r)[J+1] - V(r+1)[J]
             float gs[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -515,8 +529,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             // k0 (V(r)[J], V(r+1)[J+1], V(r+2)[J+2])   k2 (V(r+1)[J+1], V(r)[J], V(r-1)[J-1])
             // k1 (V(r+1)[J], V(r)[J+1], V(r-1)[J+2])   k3 (V(r)[J+1], V(r+1)[J], V(r+2)[J-1])
             float d0, d1, d0c, d0b, a0, a1, a1c, a1b;
-            line_adj(gpX_m3[0], gs[0], dd1s_r1, gpX_m3[2], gs[2], dd1_r, g1, d0, d1, d0c, d0b);   // main diagonal
-            line_adj(gpX_m3[1], gs[1], dd2s_r, gpX_m3[3], gs[3], dd2_r1, -g2, a0, a1, a1c, a1b);  // anti-diagonal
+            line_adj(gpX_m3[0], gs[0], dd1s_r1, gpX_m3[2], gs[2], dd1_r, f1, d0, d1, d0c, d0b);   // main diagonal
+            line_adj(gpX_m3[1], gs[1], dd2s_r, gpX_m3[3], gs[3], dd2_r1, f2, a0, a1, a1c, a1b);   // anti-diagonal
             accV_m4 += nbR(d0b) + nbL(nbL(a1c));
             accV_m3 += d0 + nbL(a1);
             accV_m2 += a0 + nbL(d1);
@@ -564,8 +578,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             gtA_m1[k] = gtA[k]; gpA_m1[k] = gpA[k]; qA_m1[k] = qA[k]; qB_m1[k] = qB[k];
             gtX_m4[k] = gtX_m3[k]; gtX_m3[k] = gtX_m2[k]; gpX_m3[k] = gpX_m2[k];
         }
-        geoB_gv = nB_gv; geoB_ddd = nB_ddd; geoB_ddu = nB_ddu; geoB_gh = nB_gh; geoB_ddr = nB_ddr; geoB_ddl = nB_ddl;
-        geoA_gv = nA_gv; geoA_ddd = nA_ddd; geoA_ddu = nA_ddu; geoA_gh = nA_gh; geoA_ddr = nA_ddr; geoA_ddl = nA_ddl;
+        geoB_fv = nB_fv; geoB_ddd = nB_ddd; geoB_ddu = nB_ddu; geoB_fh = nB_fh; geoB_ddr = nB_ddr; geoB_ddl = nB_ddl;
+        geoA_fv = nA_fv; geoA_ddd = nA_ddd; geoA_ddu = nA_ddu; geoA_fh = nA_fh; geoA_ddr = nA_ddr; geoA_ddl = nA_ddl;
         accX_m2 = accX_m1; accX_m1 = accX_0; accX_0 = accX_p1;
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
     };

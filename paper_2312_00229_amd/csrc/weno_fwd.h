@@ -70,7 +70,7 @@ constexpr bool io_scaled(int io) { return io == kIoU8F32 || io == kIoF32U8; }
 constexpr uint32_t kOob = 0x80000000u;
 
 struct FwdParams {
-    float eps_hat;  // adjoint: eps*12/13 / (1 + 4w), in the kernel's value scale
+    float eps_hat;  // adjoint: eps*3/13 / (1 + 4w), in the kernel's value scale
     float eps_q;    // doubling: eps / (4 (1 + 4w)), in the kernel's value scale
     float w;        // neighbour-indicator weight
     float beta;     // used by the general-beta path
@@ -145,11 +145,8 @@ __device__ __forceinline__ float blend4(float t0, float t1, float t2, float t3,
     return N * rcp(S);
 }
 
-// candidate (a+b)/2 - dd/8 given m = (a+b)/2, and the scaled indicator
-__device__ __forceinline__ float cand(float dd, float m) { return __builtin_fmaf(dd, -0.125f, m); }
+// scaled indicator: a second difference squared plus the slope term gc
 __device__ __forceinline__ float sidx(float dd, float gc) { return __builtin_fmaf(dd, dd, gc); }
-// g^2 * 12/13 + eps_hat
-__device__ __forceinline__ float gterm(float g, float eps_hat) { return __builtin_fmaf(g * g, 12.0f / 13.0f, eps_hat); }
 
 // The doubling's scaled copies (see the header comment): h = v/2, s = kappa v
 constexpr float kKappa = 0.52041649986653320f;    // sqrt(13/48)
