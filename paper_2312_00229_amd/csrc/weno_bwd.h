@@ -179,11 +179,16 @@ __device__ __forceinline__ float blend_seed(const float (&t)[4], const float (&p
     const float e0 = __builtin_fmaf(om[3], d03, __builtin_fmaf(om[2], d02, om[1] * d01));
     const float e1 = __builtin_fmaf(om[3], d13, __builtin_fmaf(om[2], d12, -(om[0] * d01)));
     const float e2 = __builtin_fmaf(om[3], d23, -__builtin_fmaf(om[1], d12, om[0] * d02));
-    const float e3 = -__builtin_fmaf(om[2], d23, __builtin_fmaf(om[1], d13, om[0] * d03));
-    dk[0] = (om[0] * e0) * r[0];
-    dk[1] = (om[1] * e1) * r[1];
-    dk[2] = (om[2] * e2) * r[2];
-    dk[3] = (om[3] * e3) * r[3];
+    const float oe0 = om[0] * e0, oe1 = om[1] * e1, oe2 = om[2] * e2;
+    // The omega_k (p_k - u) sum to zero (a sum of omega_k omega_j (p_k - p_j)
+    // over ordered pairs), so the last is minus the sum of the others.  Its
+    // rounding error is ~1e-7 of the largest of them, and it is scaled by
+    // 1/t_3 no more than the largest is scaled by its own 1/t_k.
+    const float oe3 = -((oe0 + oe1) + oe2);
+    dk[0] = oe0 * r[0];
+    dk[1] = oe1 * r[1];
+    dk[2] = oe2 * r[2];
+    dk[3] = oe3 * r[3];
     return u;
 }
 
@@ -299,6 +304,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     float accX_m2 = 0, accX_m1 = 0, accX_0 = 0;          // dL/dx rows s-2, s-1, s
     float gtX_m4[4] = {}, gtX_m3[4] = {}, gpX_m3[4] = {};
     float accV_m4 = 0, accV_m3 = 0, accV_m2 = 0, accV_m1 = 0, accV_0 = 0;  // dL/dV rows s-4 .. s
+    // the phase-1 term of dL/dV row s-1 from column J-2, kept until row s-1 completes
+    float dcV_m3 = 0, dcV_m2 = 0, dcV_m1 = 0;
     float fold_top = 0, held = 0;
 
     // Pacing by wave priority, as in the doubling: waves sharing a SIMD are
@@ -455,6 +462,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         // accumulators start at -0: -0 + x is x for every x, so the first sum is free
         float accX_p1 = -0.0f, accV_p1 = -0.0f;
         float gtX_m2[4] = {}, gpX_m2[4] = {};
+        float dcV_0 = 0.0f;
         if constexpr (FULL) {
         // -beta folds into the seed first (exact for beta = 1 and 2)
         const float gAb = -beta * gA, gBb = -beta * gB;
@@ -531,10 +539,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             float d0, d1, d0c, d0b, a0, a1, a1c, a1b;
             line_adj(gpX_m3[0], gs[0], dd1s_r1, gpX_m3[2], gs[2], dd1_r, f1, d0, d1, d0c, d0b);   // main diagonal
             line_adj(gpX_m3[1], gs[1], dd2s_r, gpX_m3[3], gs[3], dd2_r1, f2, a0, a1, a1c, a1b);   // anti-diagonal
-            accV_m4 += nbR(d0b) + nbL(nbL(a1c));
+            // dL/dV row s-4 takes a1c from column J-2 now and d0c from
+            // column J-2 three steps ago (kept in dcV_m3): one double shift
+            accV_m4 += nbR(d0b) + nbL(nbL(a1c + dcV_m3));
             accV_m3 += d0 + nbL(a1);
             accV_m2 += a0 + nbL(d1);
-            accV_m1 += nbL(nbL(d0c)) + nbR(a1b);
+            accV_m1 += nbR(a1b);
+            dcV_0 = d0c;
         }
 
         // ======================= dL/dV row s-4 is complete =======================
@@ -582,6 +593,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         geoA_fv = nA_fv; geoA_ddd = nA_ddd; geoA_ddu = nA_ddu; geoA_fh = nA_fh; geoA_ddr = nA_ddr; geoA_ddl = nA_ddl;
         accX_m2 = accX_m1; accX_m1 = accX_0; accX_0 = accX_p1;
         accV_m4 = accV_m3; accV_m3 = accV_m2; accV_m2 = accV_m1; accV_m1 = accV_0; accV_0 = accV_p1;
+        dcV_m3 = dcV_m2; dcV_m2 = dcV_m1; dcV_m1 = dcV_0;
     };
     using Full = std::integral_constant<int, 0>;
     using No = std::integral_constant<bool, false>;
