@@ -89,7 +89,7 @@ typedef struct {
                      [0, 64].  The paper's images use 2, its convergence
                      table 1.  With beta > 0, eps = k_eps h^2 must be > 0 and
                      keep the sum of four weights finite in FP32:
-                     beta * log2((12/13) eps) >= -124 (WENO_EINVAL otherwise;
+                     beta * log2((3/13) eps) >= -124 (WENO_EINVAL otherwise;
                      e.g. beta <= 4 at eps = 1e-8).                           */
     float k_eps;  /* eps_h = k_eps * h^2 (Section 2, eq. IzrazOmega); >= 0,
                      the paper's usual value 1e-8                              */

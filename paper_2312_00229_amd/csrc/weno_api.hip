@@ -275,10 +275,11 @@ int wz_check_params(const weno_params_t* p)
     if (!std::isfinite(p->nbw)) return WENO_EINVAL;
     if (p->boundary != WENO_BOUNDARY_CLAMP && p->boundary != WENO_BOUNDARY_EXTERNAL) return WENO_EINVAL;
     const double eps = (double)p->k_eps * (double)p->h * (double)p->h;
-    // The kernels weigh with alpha = t^-beta, t = (12/13)(eps + D) >= (12/13) eps
-    // on the [0,1] scale, and sum four of them: keep 4 t^-beta below 2^126 so
-    // that the sum stays finite in FP32 where every indicator vanishes.
-    if (p->beta > 0.0f && (eps <= 0.0 || std::log2(eps * (12.0 / 13.0)) * (double)p->beta < -124.0))
+    // The kernels weigh with alpha = t^-beta for a scaled t = c (eps + D) on the
+    // [0,1] scale (c = 1/4 in the doubling, 3/13 in its adjoint, 1 in the
+    // resampler), and sum four of them: keep 4 ((3/13) eps)^-beta below 2^126
+    // so that the sum stays finite in FP32 where every indicator vanishes.
+    if (p->beta > 0.0f && (eps <= 0.0 || std::log2(eps * (3.0 / 13.0)) * (double)p->beta < -124.0))
         return WENO_EINVAL;
     return WENO_OK;
 }

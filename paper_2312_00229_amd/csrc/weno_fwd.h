@@ -31,8 +31,8 @@
 // the mean nor the 13/12 of the indicator costs an instruction.  The common
 // factor 1/4 cancels in the normalised weights; eps is folded into every SI/4
 // as eps_q = eps / (4 (1 + 4w)), so SI/4_self + w * sum SI/4_nbr = (D + eps)/4.
-// (The adjoint carries SI' = (12/13) SI instead, with eps_hat = eps*12/13 /
-// (1 + 4w), so that SI'_self + w * sum SI'_nbr = (12/13)(D + eps).)
+// (The adjoint carries SI* = (3/13) SI instead, with eps_hat = eps*3/13 /
+// (1 + 4w), so that SI*_self + w * sum SI*_nbr = (3/13)(D + eps).)
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -106,13 +106,15 @@ def _plan_status(p):
 
 
 def test_weight_sum_limit():
-    # four weights t^-beta at the smallest t = (12/13) eps must sum below FP32's
-    # range: 4 ((12/13) eps)^-beta < 2^126
-    assert _plan_status(_p(beta=64.0, keps=0.273)) == _lib.WENO_EINVAL    # each weight ~2^127
-    assert _plan_status(_p(beta=64.0, keps=0.35)) == _lib.WENO_ENOSPC     # ~2^104: accepted
+    # four weights t^-beta at the smallest scaled t of any kernel, (3/13) eps
+    # (the adjoint's; the doubling's is eps/4), must sum below FP32's range:
+    # 4 ((3/13) eps)^-beta < 2^126
+    assert _plan_status(_p(beta=64.0, keps=0.35)) == _lib.WENO_EINVAL     # each weight ~2^232
+    assert _plan_status(_p(beta=64.0, keps=1.1)) == _lib.WENO_EINVAL      # ~2^126.6
+    assert _plan_status(_p(beta=64.0, keps=1.2)) == _lib.WENO_ENOSPC      # ~2^118.5: accepted
     assert _plan_status(_p(beta=2.0, keps=1e-8)) == _lib.WENO_ENOSPC
-    assert _plan_status(_p(beta=4.0, keps=1e-8)) == _lib.WENO_ENOSPC     # 2^110
-    assert _plan_status(_p(beta=5.0, keps=1e-8)) == _lib.WENO_EINVAL     # 2^137
+    assert _plan_status(_p(beta=4.0, keps=1e-8)) == _lib.WENO_ENOSPC     # 2^114.8
+    assert _plan_status(_p(beta=5.0, keps=1e-8)) == _lib.WENO_EINVAL     # 2^143.5
 
 
 def test_batched_noalloc_errors():
