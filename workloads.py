@@ -37,13 +37,6 @@ def smooth_grid(n: int, margin: int = 0):
     return smooth_f(X, Y)
 
 
-def smooth_fine(n: int):
-    """f at the 2n x 2m fine positions x = k/(2(n-1)), k in [0, 2n)."""
-    k = np.arange(2 * n) / (2.0 * (n - 1))
-    X, Y = np.meshgrid(k, k, indexing="ij")
-    return smooth_f(X, Y)
-
-
 # --------------------------------------------------------------------------
 # polygon scene (RGB, uint8, HWC)
 # --------------------------------------------------------------------------
