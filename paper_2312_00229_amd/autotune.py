@@ -6,11 +6,14 @@ strips amortise the 9-row pipeline fill, shorter ones give more waves to fill
 the 256 CUs; two columns per lane halve the halo overhead per wave but double
 its registers.  Every configuration computes every quad with the same
 arithmetic, so outputs are bit-identical across configurations; the tuner
-checks that too (a cheap guard against a broken configuration).
+checks that too (a cheap guard against a broken configuration).  The
+automatic configuration (the library's cost model, which alone can add
+one-column tail strips) is one of the candidates, recorded as (0, 0), so
+tuning never leaves a shape slower than the default.
 
 `tune_backward` picks the adjoint kernel's strip height (its own setting;
-it always runs one column per lane), checking that the gradient stays
-bit-identical.  `tune_batched` does the same for a
+it always runs one column per lane; the automatic height is a candidate,
+recorded as 0), checking that the gradient stays bit-identical.  `tune_batched` does the same for a
 batched plan (the persistent kernel over a
 work queue): plans capture the configuration when they are made, so it builds
 one plan per candidate, checks that all outputs stay bit-identical and leaves
@@ -98,7 +101,8 @@ def _time(fn, reps: int) -> float:
 
 def tune(x: torch.Tensor, out: torch.Tensor, reps: int = 30, use_cache: bool = True, verbose: bool = False):
     """Pick and apply the fastest (rows_per_strip, cols_per_lane) for zooming x
-    into out.  Returns (rows, cols, {config: ms})."""
+    into out, (0, 0) being the automatic configuration.  Returns (rows, cols,
+    {config: ms})."""
     key = _key(x, out)
     cache = _load_cache(use_cache)
     if use_cache and key in cache:
@@ -109,19 +113,18 @@ def tune(x: torch.Tensor, out: torch.Tensor, reps: int = 30, use_cache: bool = T
     times = {}
     ref = None
     _warm(lambda: zoom2x_(x, out))
-    for cols in COLS:
-        for rows in ROWS:
-            set_launch_config(rows, cols)
-            zoom2x_(x, out)
-            torch.cuda.synchronize()
-            if ref is None:
-                ref = out.clone()
-            elif not torch.equal(out, ref):
-                set_launch_config(*prev)
-                raise RuntimeError("launch configuration (%d, %d) changed the result" % (rows, cols))
-            times["%d,%d" % (rows, cols)] = _time(lambda: zoom2x_(x, out), reps)
-            if verbose:
-                print("rows %4d cols %d: %.4f ms" % (rows, cols, times["%d,%d" % (rows, cols)]), flush=True)
+    for rows, cols in [(0, 0)] + [(r, c) for c in COLS for r in ROWS]:
+        set_launch_config(rows, cols)
+        zoom2x_(x, out)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            set_launch_config(*prev)
+            raise RuntimeError("launch configuration (%d, %d) changed the result" % (rows, cols))
+        times["%d,%d" % (rows, cols)] = _time(lambda: zoom2x_(x, out), reps)
+        if verbose:
+            print("rows %4d cols %d: %.4f ms" % (rows, cols, times["%d,%d" % (rows, cols)]), flush=True)
     best = min(times, key=times.get)
     rows, cols = (int(t) for t in best.split(","))
     set_launch_config(rows, cols)
@@ -178,8 +181,8 @@ def tune_batched(xs, outs, params=None, reps: int = 5, use_cache: bool = True, v
 
 def tune_backward(x, grad_y, reps: int = 5, use_cache: bool = True, verbose: bool = False):
     """Pick and apply the fastest strip height for the adjoint of zooming x
-    (gradient grad_y of the output); the forward's configuration is left
-    alone.  Returns (rows, {rows: ms})."""
+    (gradient grad_y of the output), 0 being the automatic height; the
+    forward's configuration is left alone.  Returns (rows, {rows: ms})."""
     h, w = x.shape[-2:]
     planes = int(x.numel() // (h * w))
     cls = "%dx%d" % (2 ** max(0, round(math.log2(max(h, 1)))), 2 ** max(0, round(math.log2(max(w, 1)))))
@@ -192,7 +195,7 @@ def tune_backward(x, grad_y, reps: int = 5, use_cache: bool = True, verbose: boo
     prev = get_backward_launch_config()
     times = {}
     ref = None
-    for rows in ROWS_BACKWARD:
+    for rows in (0,) + ROWS_BACKWARD:
         set_backward_launch_config(rows)
         if ref is None:
             _warm(lambda: zoom2x_backward(x, grad_y))

@@ -1,6 +1,7 @@
-"""GPU tests of the launch-configuration autotuner (single images and
-batched plans): it picks one of its candidate configurations, applies it,
-caches it, and every configuration it tries gives bit-identical outputs."""
+"""GPU tests of the launch-configuration autotuner (single images,
+batched plans and the adjoint): it picks one of its candidate configurations
+(the automatic one among them), applies it, caches it, and every
+configuration it tries gives bit-identical outputs."""
 import numpy as np
 import pytest
 import torch
@@ -26,9 +27,11 @@ def test_tune_single_image(gpu, tune_cache):
         gpu.set_launch_config(0, 0)
         ref = gpu.zoom2x(x)
         rows, cols, times = autotune.tune(x, out, reps=2)
-        assert (rows, cols) in {(r, c) for r in autotune.ROWS for c in autotune.COLS}
+        # the fixed configurations and the automatic one, (0, 0)
+        assert (rows, cols) in {(r, c) for r in autotune.ROWS for c in autotune.COLS} | {(0, 0)}
         assert gpu.get_launch_config() == (rows, cols)
-        assert len(times) == len(autotune.ROWS) * len(autotune.COLS)
+        assert len(times) == len(autotune.ROWS) * len(autotune.COLS) + 1
+        assert "0,0" in times
         assert torch.equal(gpu.zoom2x(x), ref)
         assert tune_cache.exists()
         gpu.set_launch_config(0, 0)
@@ -73,8 +76,8 @@ def test_tune_backward(gpu, tune_cache):
         gpu.set_launch_config(0, 0)
         ref = gpu.zoom2x_backward(x, g)
         rows, times = autotune.tune_backward(x, g, reps=2)
-        assert rows in autotune.ROWS_BACKWARD
-        assert len(times) == len(autotune.ROWS_BACKWARD)
+        assert rows in (0,) + autotune.ROWS_BACKWARD                # 0: the automatic height
+        assert len(times) == len(autotune.ROWS_BACKWARD) + 1
         assert gpu.get_backward_launch_config() == rows
         assert gpu.get_launch_config() == (0, 0)                       # the forward is left alone
         assert torch.equal(gpu.zoom2x_backward(x, g), ref)
