@@ -26,7 +26,8 @@ struct BwdArgs {
 template <int BETA>
 __global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C, int64_t x_n, int64_t x_c,
                                                             int64_t gy_n, int64_t gy_c, int64_t gx_n, int64_t gx_c,
-                                                            int strips_x, int strips_y, int rows, FwdParams P)
+                                                            int strips_x, int strips_y, int rows, int top_rows,
+                                                            FwdParams P)
 {
     __shared__ bwd_f32x4 ring[kWavesPerBlock * kBwdRingWords];
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
@@ -41,8 +42,9 @@ __global__ __launch_bounds__(kBlock) void zoom2x_bwd_kernel(BwdArgs base, int C,
     cx.x_h = base.x_h; cx.gy_h = base.gy_h; cx.gx_h = base.gx_h;
     cx.x_w = base.x_w; cx.gy_w = base.gy_w; cx.gx_w = base.gx_w;
     cx.H = base.H; cx.W = base.W;
-    const int R0 = sy * rows;
-    const int R1 = min(R0 + rows, cx.H);
+    // band 0 holds top_rows rows, the others rows each (the last what is left)
+    const int R0 = sy == 0 ? 0 : top_rows + (sy - 1) * rows;
+    const int R1 = min(sy == 0 ? top_rows : R0 + rows, cx.H);
     bwd_strip<BETA>(cx, P, sx, R0, R1, ring + (threadIdx.x >> 6) * kBwdRingWords);
 }
 
@@ -72,36 +74,67 @@ BwdDevice bwd_device()
     return {cus, per_cu > 0 ? per_cu : 1};
 }
 
-// Strip height of the adjoint.  Every strip walks rows + kBwdWarm steps, the
-// first of them forward only, and all strips take about the same time.  The
-// blocks spread evenly over the CUs, so the busiest CU holds
-// k = ceil(blocks / CUs) of them and runs them two at a time (one at a time
-// where only one fits); a wave that shares its SIMD with another takes about
-// 1.5x as long per row as a wave alone on it (measured on MI355X: ~1.8 us
-// against ~1.2 us per row), so a launch costs about
-//   (1.5 x shared rounds + lone rounds) x (rows + kBwdWarmCost).
-// The band count that minimises it wins (the fewest bands on a tie).  A
-// launch of just over one block per CU thus pays for the pairs it forms: at
-// 3x256x256 the model picks 5-row strips (234 blocks, all alone, 26 us)
-// over 4-row ones (288 blocks, 32 CUs with two, 36 us).
+// Bands of the adjoint: a walk over rows [R0, R1) takes R1 - R0 + 18 steps
+// in the middle of a plane, 4 more in the top band (it starts four rows
+// earlier to fold the padded rows -4..-1) and 5 more in the bottom one (it
+// walks on to fold the padded rows H..H+4).  So the top band is made 4 rows
+// shorter than the others and the automatic height leaves the bottom band
+// about 5 short, and every band walks about as long.
+struct BwdBands {
+    int rows, top, count;   // height of the bands after the first, of the first, and their number
+};
+
+BwdBands bwd_bands(int H, int rows)
+{
+    if (rows >= H) return {H, H, 1};
+    int top = rows - (kBwdWarmTop - kBwdWarm);
+    if (top < 1) top = 1;
+    return {rows, top, 1 + (H - top + rows - 1) / rows};
+}
+
+// Longest walk of a band layout, in rows plus the extra steps of the top and
+// bottom bands (see bwd_bands); the warm-up every band walks is left out.
+int bwd_longest_band(int H, const BwdBands& b)
+{
+    if (b.count == 1) return H + 9;
+    const int last = H - b.top - (b.count - 2) * b.rows;
+    const int edge = b.top + 4 > last + 5 ? b.top + 4 : last + 5;
+    return b.count == 2 || edge > b.rows ? edge : b.rows;
+}
+
+// Strip height of the adjoint.  Every strip walks its rows plus kBwdWarm
+// steps, the first of them forward only.  The blocks spread evenly over the
+// CUs, so the busiest CU holds k = ceil(blocks / CUs) of them and runs them
+// two at a time (one at a time where only one fits); a wave that shares its
+// SIMD with another takes about 1.5x as long per row as a wave alone on it
+// (measured on MI355X: ~1.8 us against ~1.2 us per row), so a launch costs
+// about
+//   (1.5 x shared rounds + lone rounds) x (longest band walk + kBwdWarmCost).
+// Candidates: for each band count b, bands of ceil((H + 9) / b) rows (the
+// edge bands then walk about as long as the others) and of ceil(H / b); the
+// cheapest layout wins (the first found on a tie).  A launch of just over
+// one block per CU thus pays for the pairs it forms: at 3x256x256 the model
+// takes all-alone short strips over a layout that puts two blocks on some
+// CUs.
 int bwd_auto_rows(int H, int strips_x, int64_t planes, BwdDevice dev)
 {
     int best_rows = H;
     int64_t best = INT64_MAX;
     const int max_b = H < 1024 ? H : 1024;
     for (int b = 1; b <= max_b; ++b) {
-        const int rows = (H + b - 1) / b;
-        if (b > 1 && rows < 4) break;   // one band always qualifies
-        const int bands = (H + rows - 1) / rows;
-        if (bands != b) continue;   // same strips as a smaller band count
-        const int64_t blocks = planes * (((int64_t)strips_x * bands + kWavesPerBlock - 1) / kWavesPerBlock);
-        const int64_t k = (blocks + dev.cus - 1) / dev.cus;
-        const int64_t shared = dev.per_cu >= 2 ? k / 2 : 0;
-        const int64_t alone = k - 2 * shared;
-        const int64_t cost = (3 * shared + 2 * alone) * (rows + kBwdWarmCost);
-        if (cost < best) {
-            best = cost;
-            best_rows = rows;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int rows = b == 1 ? H : (pass == 0 ? (H + 9 + b - 1) / b : (H + b - 1) / b);
+            if (rows < 4 && b > 1) continue;
+            const BwdBands bands = bwd_bands(H, rows);
+            const int64_t blocks = planes * (((int64_t)strips_x * bands.count + kWavesPerBlock - 1) / kWavesPerBlock);
+            const int64_t k = (blocks + dev.cus - 1) / dev.cus;
+            const int64_t shared = dev.per_cu >= 2 ? k / 2 : 0;
+            const int64_t alone = k - 2 * shared;
+            const int64_t cost = (3 * shared + 2 * alone) * (bwd_longest_band(H, bands) + kBwdWarmCost);
+            if (cost < best) {
+                best = cost;
+                best_rows = rows;
+            }
         }
     }
     return best_rows;
@@ -170,20 +203,23 @@ extern "C" int weno_zoom2x_backward(const weno_tensor_t* x, const weno_tensor_t*
     int rows = bwd_auto_rows(x->h, strips_x, planes, bwd_device());
     const int explicit_rows = g_bwd_rows.load();
     if (explicit_rows > 0) rows = explicit_rows;
-    const int strips_y = (x->h + rows - 1) / rows;
+    const BwdBands bands = bwd_bands(x->h, rows);
+    const int strips_y = bands.count;
     dim3 grid((strips_x * strips_y + kWavesPerBlock - 1) / kWavesPerBlock, x->n * x->c);
     hipStream_t st = (hipStream_t)hip_stream;
     const int bm = wz_beta_mode(p->beta);
     if (bm == 2)
         hipLaunchKernelGGL(zoom2x_bwd_kernel<2>, grid, dim3(kBlock), 0, st, cx, x->c, x->sn * 4, x->sc * 4,
-                           grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x, strips_y, rows, P);
+                           grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x, strips_y, bands.rows,
+                           bands.top, P);
     else if (bm == 1)
         hipLaunchKernelGGL(zoom2x_bwd_kernel<1>, grid, dim3(kBlock), 0, st, cx, x->c, x->sn * 4, x->sc * 4,
-                           grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x, strips_y, rows, P);
+                           grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x, strips_y, bands.rows,
+                           bands.top, P);
     else
         hipLaunchKernelGGL(zoom2x_bwd_kernel<kBetaGeneral>, grid, dim3(kBlock), 0, st, cx, x->c, x->sn * 4,
                            x->sc * 4, grad_y->sn * 4, grad_y->sc * 4, grad_x->sn * 4, grad_x->sc * 4, strips_x,
-                           strips_y, rows, P);
+                           strips_y, bands.rows, bands.top, P);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wz_hip_error(e, "zoom2x_bwd_kernel launch");
     return WENO_OK;
