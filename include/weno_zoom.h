@@ -273,10 +273,13 @@ int weno_query_launch_config(const weno_tensor_t* src, const weno_tensor_t* dst,
  * Strip height of the adjoint kernel (weno_zoom2x_backward; process-global,
  * read at each call), independent of the forward's configuration.  The
  * adjoint always runs one column per lane.
- *   rows_per_strip: input rows one wave walks, in [4, 4096]; 0 selects the
- *                   automatic choice (the default): the height that minimises
- *                   the rounds of resident waves times the rows each wave
- *                   walks.
+ *   rows_per_strip: input rows one wave walks, in [4, 4096]; the top band of
+ *                   a plane takes 4 rows fewer (at least 1), since it walks
+ *                   4 extra steps to fold the padded rows above the image,
+ *                   and the bottom band what is left.  0 selects the
+ *                   automatic choice (the default): the height that
+ *                   minimises the rounds of resident waves times the
+ *                   longest band walk.
  * Gradients are bit-identical across strip heights.  Returns WENO_EINVAL for
  * values outside these sets.
  */
