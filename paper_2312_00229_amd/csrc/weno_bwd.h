@@ -290,7 +290,7 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // registers: slot s & 3 holds them from step s until step s+4 reads it
     // and then overwrites it with its own (each lane reads and writes only its
     // own words, so program order is all the ordering needed).
-    auto ring_at = [&](int s, int half) -> bwd_f32x4& { return ring[((s & 3) * 2 + half) * kWave + lane]; };
+    auto ring_at = [&](int slot, int half) -> bwd_f32x4& { return ring[(slot * 2 + half) * kWave + lane]; };
     // The diagonal second differences of input row r, {dd1, dd2s, dd1s, dd2}
     // (dd1, dd2 centred at (r, J), dd1s, dd2s at (r, J+1)), made when row r
     // enters the pipeline (step r-4) and read by the phase-1 adjoints of
@@ -331,12 +331,19 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // differences of the + points from -2 and the + points from -1.
     // P1 = false (full iterations only): skip the phase-1 stencil adjoint and
     // the output, which reach only rows this strip never stores
-    auto step = [&](const int s, auto dconst, auto p1) {
+    int s_ref = 0;   // the seed-factor ring's slot of step s is (s - s_ref) & 3
+    auto step = [&](const int s, auto dconst, auto p1, auto slotc) {
         constexpr int D = decltype(dconst)::value;
         constexpr bool FULL = D == 0;
         constexpr bool do_dd = FULL || D >= -7, do_sx = FULL || D >= -6, do_x = FULL || D >= -4;
         constexpr bool do_p2dd = FULL || D >= -2, do_p2 = FULL || D >= -1;
-        constexpr bool P1 = decltype(p1)::value;
+        constexpr int P1M = decltype(p1)::value;
+        constexpr bool P1 = P1M != 0, INTERIOR = P1M == 2;
+        // slot of the seed-factor ring: (s - s_ref) & 3, a constant in the
+        // interior trips (their steps are s_ref + 4i + k)
+        int slot;
+        if constexpr (std::is_integral<decltype(slotc)>::value) slot = (s - s_ref) & 3;
+        else slot = decltype(slotc)::value;
         const float V5 = 0.5f * Q0;
         Q0 = Q1;
         Q1 = ldV(s + 7);
@@ -350,8 +357,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             ddm2 = dd_at(s - 2, 1);
         }
         if constexpr (FULL) {
-            omXr = ring_at(s, 0);
-            dkXr = ring_at(s, 1);
+            omXr = ring_at(slot, 0);
+            dkXr = ring_at(slot, 1);
             gA = nA; gB = nB; gXu = nX; gVu = nV;
             nA = ldG(2 * s + 3, gyoffA);
             nB = ldG(2 * s + 2, gyoffB);
@@ -399,8 +406,8 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             // forward-only ones leave unwritten, and their seeds reach only
             // phase-1 adjoints that are skipped.
             if constexpr (FULL) {
-                ring_at(s, 0) = bwd_f32x4{omX2[0], omX2[1], omX2[2], omX2[3]};
-                ring_at(s, 1) = bwd_f32x4{dkX2[0], dkX2[1], dkX2[2], dkX2[3]};
+                ring_at(slot, 0) = bwd_f32x4{omX2[0], omX2[1], omX2[2], omX2[3]};
+                ring_at(slot, 1) = bwd_f32x4{dkX2[0], dkX2[1], dkX2[2], dkX2[3]};
             }
         }
         float ddXv1 = 0.0f, ddr1 = 0.0f;
@@ -565,13 +572,19 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
                 for (int k = 0; k < 5; ++k) { q = nbR(q); acc += q; }
                 if (J == W - 1) val += acc;
             }
-            // clamped rows: rows -4..-1 fold onto row 0, rows H..H+4 onto row H-1
-            if (top && r < 0) {
-                if (r >= -4) fold_top += val;   // padded rows -4..-1; earlier rows are pipeline fill
+            // clamped rows: rows -4..-1 fold onto row 0, rows H..H+4 onto row
+            // H-1; interior steps store rows in [R0, R1) that fold nothing
+            if constexpr (INTERIOR) {
+                if (own) stG(r, val);
+            } else if (top && r <= 0 && r < H - 1) {
+                if (r < 0) {
+                    if (r >= -4) fold_top += val;   // padded rows -4..-1; earlier rows are pipeline fill
+                } else if (own) {
+                    stG(0, val + fold_top);
+                }
             } else if (bottom && r >= H - 1) {
                 held += (r == H - 1 && top && H == 1) ? val + fold_top : val;
             } else if (r >= R0 && r < R1) {
-                if (top && r == 0) val += fold_top;
                 if (own) stG(r, val);
             }
         }
@@ -596,14 +609,19 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         dcV_m3 = dcV_m2; dcV_m2 = dcV_m1; dcV_m1 = dcV_0;
     };
     using Full = std::integral_constant<int, 0>;
-    using No = std::integral_constant<bool, false>;
-    using Yes = std::integral_constant<bool, true>;
+    using No = std::integral_constant<int, 0>;        // no phase-1 adjoint, no output
+    using P1All = std::integral_constant<int, 1>;     // phase-1 adjoint, output with the edge folds
+    using P1In = std::integral_constant<int, 2>;      // phase-1 adjoint, interior output row
+    using K0 = std::integral_constant<int, 0>;
+    using K1 = std::integral_constant<int, 1>;
+    using K2 = std::integral_constant<int, 2>;
+    using K3 = std::integral_constant<int, 3>;
     static_assert(kBwdForwardOnly == 9, "the forward-only iterations are D = -9 .. -1");
     {
         const int s0 = s;
         auto fwd_only = [&](auto dconst) {
             constexpr int D = decltype(dconst)::value;
-            if (s0 + 9 + D <= s_end) step(s0 + 9 + D, dconst, No{});
+            if (s0 + 9 + D <= s_end) step(s0 + 9 + D, dconst, No{}, 0);
         };
         fwd_only(std::integral_constant<int, -9>{});
         fwd_only(std::integral_constant<int, -8>{});
@@ -625,25 +643,33 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // folded rows -4 .. -1) both reach only rows this strip never stores, so
     // those iterations (the 6 after the forward-only ones) skip them.
     const int s_p1 = min(top ? -3 : R0 + 1, s_end + 1);
+    // Interior steps [s_in0, s_in1) store a row of [R0, R1) that takes no
+    // fold (rows 1.. of the top strip, up to H-2 in the bottom one); the
+    // steps around them run the output with the edge folds.
+    const int s_in0 = min(top ? 5 : R0 + 4, s_end + 1);
+    const int s_in1 = max(s_in0, min(bottom ? H + 3 : R1 + 4, s_end + 1));
+    s_ref = s_in0;
     for (; s + 1 < s_p1; s += 2) {
-        step(s, Full{}, No{});
-        step(s + 1, Full{}, No{});
+        step(s, Full{}, No{}, 0);
+        step(s + 1, Full{}, No{}, 0);
     }
-    if (s < s_p1) step(s++, Full{}, No{});
+    if (s < s_p1) step(s++, Full{}, No{}, 0);
+    for (; s < s_in0; ++s) step(s, Full{}, P1All{}, 0);
     // four rows per trip so that values carried up to four rows are renamed
     // rather than copied
     const int q1 = s + (s_end - s) / 4, q2 = s + (s_end - s) / 2, q3 = s + 3 * (s_end - s) / 4;
-    for (; s + 3 <= s_end; s += 4) {
+    for (; s + 3 < s_in1; s += 4) {
         if (s >= q3) __builtin_amdgcn_s_setprio(0);
         else if (s >= q2) __builtin_amdgcn_s_setprio(1);
         else if (s >= q1) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(3);
-        step(s, Full{}, Yes{});
-        step(s + 1, Full{}, Yes{});
-        step(s + 2, Full{}, Yes{});
-        step(s + 3, Full{}, Yes{});
+        step(s, Full{}, P1In{}, K0{});
+        step(s + 1, Full{}, P1In{}, K1{});
+        step(s + 2, Full{}, P1In{}, K2{});
+        step(s + 3, Full{}, P1In{}, K3{});
     }
-    for (; s <= s_end; ++s) step(s, Full{}, Yes{});
+    for (; s < s_in1; ++s) step(s, Full{}, P1In{}, 0);
+    for (; s <= s_end; ++s) step(s, Full{}, P1All{}, 0);
     if (bottom) {
         const int r = H - 1;
         if (r >= R0 && own) stG(r, held);
