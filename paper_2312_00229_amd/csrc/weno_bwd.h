@@ -290,14 +290,24 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // registers: slot s & 3 holds them from step s until step s+4 reads it
     // and then overwrites it with its own (each lane reads and writes only its
     // own words, so program order is all the ordering needed).
+    int s_ref = 0;   // ring slots count steps from s_ref (set before the first full step)
     auto ring_at = [&](int slot, int half) -> bwd_f32x4& { return ring[(slot * 2 + half) * kWave + lane]; };
     // The diagonal second differences of input row r, {dd1, dd2s, dd1s, dd2}
     // (dd1, dd2 centred at (r, J), dd1s, dd2s at (r, J+1)), made when row r
     // enters the pipeline (step r-4) and read by the phase-1 adjoints of
     // steps r+2 (the .zw half) and r+3 (the .xy half); slot r & 7 is next
     // written at step r+4.
-    auto dd_at = [&](int r, int half) -> bwd_f32x2& {
-        return reinterpret_cast<bwd_f32x2*>(ring + kBwdSeedWords + (r & 7) * kWave + lane)[half];
+    // Slot of row r: (r - s_ref) & 7.  In the interior trips (steps
+    // s_ref + 4i + k) a slot m of the trip's first step is m ^ 4 in the next
+    // trip, so dd_lo / dd_hi (slots 0..3 / 4..7 of this lane) trade places
+    // after every trip and each access is a fixed base and offset.
+    bwd_f32x2* const dd_base = reinterpret_cast<bwd_f32x2*>(ring + kBwdSeedWords + lane);
+    bwd_f32x2* dd_lo = dd_base;
+    bwd_f32x2* dd_hi = dd_base + 4 * 2 * kWave;
+    auto dd_at = [&](int r, int half) -> bwd_f32x2& { return dd_base[((r - s_ref) & 7) * 2 * kWave + half]; };
+    auto dd_at_m = [&](auto mc, int half) -> bwd_f32x2& {   // interior: slot m of the trip's frame
+        constexpr int m = decltype(mc)::value;
+        return ((m & 4) ? dd_hi : dd_lo)[(m & 3) * 2 * kWave + half];
     };
     // ---------------- adjoint state ----------------
     float gtA_m1[4] = {}, gpA_m1[4] = {}, qA_m1[4] = {}, qB_m1[4] = {};
@@ -331,7 +341,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // differences of the + points from -2 and the + points from -1.
     // P1 = false (full iterations only): skip the phase-1 stencil adjoint and
     // the output, which reach only rows this strip never stores
-    int s_ref = 0;   // the seed-factor ring's slot of step s is (s - s_ref) & 3
     auto step = [&](const int s, auto dconst, auto p1, auto slotc) {
         constexpr int D = decltype(dconst)::value;
         constexpr bool FULL = D == 0;
@@ -353,8 +362,14 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         // phase-1 adjoint, read before this step writes row s+4's slot
         bwd_f32x2 ddm3 = {}, ddm2 = {};
         if constexpr (P1) {
-            ddm3 = dd_at(s - 3, 0);
-            ddm2 = dd_at(s - 2, 1);
+            if constexpr (std::is_integral<decltype(slotc)>::value) {
+                ddm3 = dd_at(s - 3, 0);
+                ddm2 = dd_at(s - 2, 1);
+            } else {
+                constexpr int k = decltype(slotc)::value;
+                ddm3 = dd_at_m(std::integral_constant<int, (k - 3) & 7>{}, 0);
+                ddm2 = dd_at_m(std::integral_constant<int, (k - 2) & 7>{}, 1);
+            }
         }
         if constexpr (FULL) {
             omXr = ring_at(slot, 0);
@@ -372,8 +387,14 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
             dd2_4 = d2(nbR(V3), V4, nbL(V5));
             dd1s_4 = nbR(dd1_4);
             dd2s_4 = nbR(dd2_4);
-            dd_at(s + 4, 0) = bwd_f32x2{dd1_4, dd2s_4};
-            dd_at(s + 4, 1) = bwd_f32x2{dd1s_4, dd2_4};
+            if constexpr (std::is_integral<decltype(slotc)>::value) {
+                dd_at(s + 4, 0) = bwd_f32x2{dd1_4, dd2s_4};
+                dd_at(s + 4, 1) = bwd_f32x2{dd1s_4, dd2_4};
+            } else {
+                constexpr int k = decltype(slotc)::value;
+                dd_at_m(std::integral_constant<int, (k + 4) & 7>{}, 0) = bwd_f32x2{dd1_4, dd2s_4};
+                dd_at_m(std::integral_constant<int, (k + 4) & 7>{}, 1) = bwd_f32x2{dd1s_4, dd2_4};
+            }
         }
         // x row s+3
         float SX3[4] = {1, 1, 1, 1}, PX3[4] = {};
@@ -617,6 +638,13 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     using K2 = std::integral_constant<int, 2>;
     using K3 = std::integral_constant<int, 3>;
     static_assert(kBwdForwardOnly == 9, "the forward-only iterations are D = -9 .. -1");
+    // Interior steps [s_in0, s_in1) store a row of [R0, R1) that takes no
+    // fold (rows 1.. of the top strip, up to H-2 in the bottom one); the
+    // steps around them run the output with the edge folds.  The rings'
+    // slots count from s_in0, fixed before the first step writes them.
+    const int s_in0 = min(top ? 5 : R0 + 4, s_end + 1);
+    const int s_in1 = max(s_in0, min(bottom ? H + 3 : R1 + 4, s_end + 1));
+    s_ref = s_in0;
     {
         const int s0 = s;
         auto fwd_only = [&](auto dconst) {
@@ -643,12 +671,6 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
     // folded rows -4 .. -1) both reach only rows this strip never stores, so
     // those iterations (the 6 after the forward-only ones) skip them.
     const int s_p1 = min(top ? -3 : R0 + 1, s_end + 1);
-    // Interior steps [s_in0, s_in1) store a row of [R0, R1) that takes no
-    // fold (rows 1.. of the top strip, up to H-2 in the bottom one); the
-    // steps around them run the output with the edge folds.
-    const int s_in0 = min(top ? 5 : R0 + 4, s_end + 1);
-    const int s_in1 = max(s_in0, min(bottom ? H + 3 : R1 + 4, s_end + 1));
-    s_ref = s_in0;
     for (; s + 1 < s_p1; s += 2) {
         step(s, Full{}, No{}, 0);
         step(s + 1, Full{}, No{}, 0);
@@ -667,6 +689,9 @@ __device__ __forceinline__ void bwd_strip(const BwdCtx& cx, const FwdParams& P, 
         step(s + 1, Full{}, P1In{}, K1{});
         step(s + 2, Full{}, P1In{}, K2{});
         step(s + 3, Full{}, P1In{}, K3{});
+        bwd_f32x2* const t = dd_lo;
+        dd_lo = dd_hi;
+        dd_hi = t;
     }
     for (; s < s_in1; ++s) step(s, Full{}, P1In{}, 0);
     for (; s <= s_end; ++s) step(s, Full{}, P1All{}, 0);
