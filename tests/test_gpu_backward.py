@@ -126,6 +126,26 @@ def test_backward_independent_of_strip_height(gpu):
         gpu.set_launch_config(0, 0)
 
 
+@pytest.mark.parametrize("H", [1, 2, 3, 5, 6, 9])
+def test_backward_short_planes_every_band_layout(gpu, H):
+    """Planes barely taller than a band: the top band is 4 rows shorter than
+    the others (at least 1 row) and the bottom band takes what is left, so
+    these heights give one to four bands of uneven size; every layout gives
+    the same bits, and they match the oracle."""
+    rng = np.random.default_rng(40 + H)
+    V = rng.random((2, H, 70))
+    G = rng.standard_normal((2, 2 * H, 140))
+    x, g = _t(V), _t(G)
+    ref = gpu.zoom2x_backward(x, g)
+    check_adjoint(ref.cpu().numpy(), V, G, "short plane H=%d" % H)
+    try:
+        for rows in (4, 5, 6, 7, 8, 12):
+            gpu.set_backward_launch_config(rows)
+            assert torch.equal(gpu.zoom2x_backward(x, g), ref), (H, rows)
+    finally:
+        gpu.set_backward_launch_config(0)
+
+
 def test_autograd_function(gpu):
     rng = np.random.default_rng(6)
     V = rng.random((3, 24, 31))
